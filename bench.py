@@ -1,0 +1,246 @@
+"""Benchmark: nested MLMC hot path on one MI355X.
+
+Workload (default): the nested approximate-normal MLMC of a European call on GBM
+(S0 = K = 100, r = 0.05, sigma = 0.2, T = 1), Milstein, levels 0..8; the
+approximate estimator uses the Method-1 table with q = 8 (packed 8-bit indices,
+four per 32-bit word) in FP32, the correction estimator FP64 minus FP32 on the same
+uniforms; N_l (approximate) and M_l (correction) come from the nested optimal
+allocation at eps = 1e-3 in price units (variance eps^2, theta = 1) after an
+untimed pilot.  One step = all 18 (level, estimator) level sums in one launch
+sequence plus the host combination into the price estimate.
+
+Printed: one JSON line (metric path-steps/s), with the VALU roofline of the
+dominant kernel (HIP-event timing inside the timed region), the CPU oracle timed on
+a bounded sample, and the time to RMSE eps of the nested estimator against plain
+FP32 MLMC on the same GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GBM = dict(S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0)
+LEVELS = 9
+Q = 8
+EPS = 1e-3                 # price units
+SEED = 1234
+N_PILOT = 100_000
+
+# --- algorithmic VALU work per fine path-step (32-bit lane operations), by kernel
+# class.  Philox4x32-10: 10 rounds of 2 widening 32x32->64 multiplies and 4 xors
+# per block of 4 words; each multiply is weighted by its issue cost relative to a
+# full-rate 32-bit op (MUL64_COST, measured on gfx950 by the instruction probe).
+MUL64_COST = 4.0
+
+
+def philox_ops():
+    return 10 * (2 * MUL64_COST + 4)
+
+
+def alg_ops_per_step(est, fields, scheme, level):
+    """Algorithmic lane-ops per fine path-step of one coupled sample.
+    Table side (FP32, Algorithm 1 per operation): fine step mul + add (2); coarse step
+    per fine pair: zsum, mul1, sum1, mul2, X-add (5), Milstein + zsq, zm1, mul3, sum2 (9);
+    index: shift (+ mask when packed).  Per path: payoff and level difference (~8)."""
+    mil = scheme == 1
+    wpb = 4 * fields
+    ops = philox_ops() / wpb
+    coarse = (9 if mil else 5) / 2.0 if level >= 1 else 0.0
+    if est == 1:            # approximate
+        ops += (2 if fields > 1 else 1) + 2 + coarse
+    return ops + 8.0 / (1 << level)
+
+
+def peak_valu():
+    """Full-rate 32-bit VALU lane-ops/s of MI355X: 256 CUs x 128 lanes/clk x 2.4 GHz
+    (the 157.3 TFLOP/s FP32 vector figure is 78.6e12 FMA lane-ops/s)."""
+    return 256 * 128 * 2.4e9
+
+
+def make_items(M, prob, prec_a, prec_c, Na, Nc, offset):
+    items = []
+    for l in range(LEVELS):
+        items.append((prob, l, int(Na[l]), offset, prec_a, M.EST_APPROX, SEED, 0))
+        items.append((prob, l, int(Nc[l]), offset, prec_c, M.EST_CORR, SEED, 0))
+    return items
+
+
+def combine(res, scale):
+    est, var = 0.0, 0.0
+    for r in res:
+        s = r["euro"]
+        n = s["n"]
+        m = s["sum1"] / n
+        v = max((s["sum2"] - s["sum1"] ** 2 / n) / (n - 1), 0.0)
+        est += m
+        var += v / n
+    return scale * est, scale * math.sqrt(var)
+
+
+def cpu_baseline(Na, Nc, budget_paths_steps=2.0e7):
+    """The oracle on a bounded sample of the same works (same levels and estimators,
+    sample sizes proportional to N_l, M_l): single-threaded numpy."""
+    import numpy as np
+    from oracle.mlmc import level_sums
+    from oracle.paths import Precision, Problem
+    p = Problem("milstein", barrier=0.0, **GBM)
+    total = sum(int(Na[l]) << l for l in range(LEVELS)) + sum(int(Nc[l]) << l for l in range(LEVELS))
+    f = min(1.0, budget_paths_steps / total)
+    t0 = time.perf_counter()
+    steps = 0
+    for l in range(LEVELS):
+        for est, N, packed in ((1, Na[l], True), (2, Nc[l], False)):
+            n = max(256, int(round(int(N) * f)))
+            level_sums(p, l, n, 0, Precision("fp32", Q, packed), est, SEED, 0, ("euro",))
+            steps += n << l
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps:.3g} fine path-steps: the 18 (level, estimator) works with N_l, M_l "
+                      f"scaled by {f:.3g} (>= 256 paths each), single-threaded numpy"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tte", action="store_true", help="skip the time-to-eps comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2502_07123_amd as M
+
+    ctx = M.Context(0, workspace_bytes=1 << 30)
+    prob = M.make_problem("milstein", ("euro",), **GBM)
+    prec_a = M.make_precision("fp32", Q, packed=True)
+    prec_c = M.make_precision("fp32", Q, packed=False)
+    scale = math.exp(-GBM["r"] * GBM["T"]) * GBM["S0"]
+    eps_int = EPS / scale
+
+    # pilot + cost calibration (untimed): variances and ns per path-step per estimator
+    ctx.set_timing(True)
+    pil = ctx.level_sums_batch(make_items(M, prob, prec_a, prec_c, [N_PILOT] * LEVELS,
+                                          [N_PILOT] * LEVELS, 0))
+    stats = ctx.kernel_stats()
+    ns = {s["estimator"]: s["ms"] * 1e6 / s["path_steps"] for s in stats}
+    c_a, c_c = ns[M.EST_APPROX], ns[M.EST_CORR]
+
+    def var(s):
+        n = s["n"]
+        return max((s["sum2"] - s["sum1"] ** 2 / n) / (n - 1), 1e-300)
+
+    Va = [var(pil[2 * l]["euro"]) for l in range(LEVELS)]
+    Vc = [var(pil[2 * l + 1]["euro"]) for l in range(LEVELS)]
+    V = np.array(Va + Vc)
+    Cst = np.array([c_a * 2 ** l for l in range(LEVELS)] + [c_c * 2 ** l for l in range(LEVELS)])
+    N = M.allocate(V, Cst, eps_int ** 2, 1.0)          # Section 2.2 allocation, theta = 1
+    Na, Nc = N[:LEVELS], N[LEVELS:]
+    path_steps = int(sum(int(Na[l]) << l for l in range(LEVELS)) + sum(int(Nc[l]) << l for l in range(LEVELS)))
+
+    off = N_PILOT
+    for w in range(args.warmup):
+        ctx.level_sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, off))
+        off += int(max(N))
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ests = []
+    for k in range(args.steps):
+        res = ctx.level_sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, off))
+        ests.append(combine(res, scale))
+        off += int(max(N))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ctx.kernel_stats()
+    ctx.set_timing(False)
+    ms_step = dt * 1e3 / args.steps
+    value = path_steps / (dt / args.steps)
+
+    # roofline of the dominant kernel (largest event time in the timed region)
+    dom = max(stats, key=lambda s: s["ms"])
+    per_launch_steps = dom["path_steps"] / dom["launches"]
+    # algorithmic ops of that kernel's works, level by level (its level mix)
+    if dom["estimator"] == M.EST_APPROX:
+        mix = [(l, int(Na[l])) for l in range(LEVELS)]
+    else:
+        mix = [(l, int(Nc[l])) for l in range(LEVELS)]
+    ops = sum(n * (1 << l) * alg_ops_per_step(dom["estimator"], dom["fields"], dom["scheme"], l)
+              for l, n in mix)
+    avg_s = dom["ms"] / dom["launches"] * 1e-3
+    achieved = ops / avg_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_valu() / 1e12,
+                "unit": "Tlane-op/s", "frac": achieved / peak_valu(), "traffic": None,
+                "kernel": {"estimator": dom["estimator"], "fields": dom["fields"],
+                           "avg_launch_ms": dom["ms"] / dom["launches"],
+                           "path_steps_per_launch": per_launch_steps,
+                           "alg_lane_ops_per_launch": ops}}
+
+    extra = {
+        "estimate": float(np.mean([e[0] for e in ests])),
+        "rmse_bound": float(ests[-1][1]),
+        "N_approx": [int(x) for x in Na], "N_corr": [int(x) for x in Nc],
+        "kernels": [{"estimator": s["estimator"], "arith": s["arith"], "fields": s["fields"],
+                     "launches": s["launches"], "ms": s["ms"],
+                     "path_steps_per_s": s["path_steps"] / (s["ms"] * 1e-3)} for s in stats],
+    }
+    if not args.no_tte:
+        extra["time_to_eps"] = time_to_eps(M, ctx, prob, prec_a, c_a, c_c)
+    cpu = None if args.no_cpu else cpu_baseline(Na, Nc)
+    line = {
+        "metric": "path-steps/s per level; time to RMSE eps, nested low-prec vs plain FP32",
+        "value": value, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "nested MLMC, European call on GBM, Milstein, levels 0..8, "
+                               "q=8 Method-1 table (packed), FP32 approx + FP64 correction, "
+                               "allocation at eps=1e-3 (price units)",
+                   "path_steps_per_step": path_steps},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+def time_to_eps(M, ctx, prob, prec_a, c_a, c_c):
+    """Wall time of one on-line MLMC estimate to RMSE eps (price units), levels 0..8,
+    nested (FP32 table + FP64 correction) vs plain FP32 (exact FP32 normals); the
+    cost model uses the calibrated ns per path-step of each kernel class."""
+    import numpy as np
+    out = {}
+    plain_stat = {}
+    ctx.set_timing(True)
+    ctx.level_sums(prob, 4, 200_000, 0, M.make_precision("fp32", Q), M.EST_PLAIN, SEED)
+    st = ctx.kernel_stats()
+    ctx.set_timing(False)
+    c_p = st[0]["ms"] * 1e6 / st[0]["path_steps"]
+    for name, nested in (("nested", True), ("plain_fp32", False)):
+        cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", theta=1.0, L_min=8, L_max=8,
+                                n_pilot=20_000, costs=(c_p, c_a, c_c), plain_arith="fp32",
+                                prec=prec_a)
+        ctx.estimate(prob, cfg, SEED + 1)                  # warm (tables, caches)
+        ts, ests = [], []
+        for rep in range(3):
+            t0 = time.perf_counter()
+            r = ctx.estimate(prob, cfg, SEED + 2 + rep)
+            ts.append(time.perf_counter() - t0)
+            ests.append(r["estimate"])
+        out[name] = {"seconds": float(np.median(ts)), "estimate": float(np.mean(ests)),
+                     "rmse_bound": math.sqrt(r["variance"]), "path_steps": r["path_steps"]}
+    out["speedup"] = out["plain_fp32"]["seconds"] / out["nested"]["seconds"]
+    out["cost_ns_per_step"] = {"plain_fp32": c_p, "approx": c_a, "corr": c_c}
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,350 @@
+/*
+ * mlmc.h -- C ABI of the MI355X nested multilevel Monte Carlo library.
+ *
+ * The library computes the data-parallel hot path of the nested MLMC method of
+ * Haas & Giles, "A nested MLMC framework for efficient simulations on FPGAs"
+ * (2025): coupled fine/coarse Geometric Brownian Motion paths (Section 2.1,
+ * Algorithm 1; Milstein as named in Section 7) driven by counter-based uniforms,
+ * mapped to normals either exactly or by the Method-1 piecewise-constant table
+ * (Section 3.1), in FP64, FP32 or per-variable fixed point (Section 4.1), and
+ * reduced into per-level sums of the payoff differences (Section 2.1) for the
+ * plain and the two nested estimators (Section 2.2).  On top sit the optimal
+ * sample allocation (Sections 2.1-2.2), an adaptive driver, batched pricing of
+ * many options in one launch per sweep, and a continuous-batching server.
+ *
+ * Units.  Paths are simulated in S0-normalised units X = S / S0; every sum below
+ * is of normalised, undiscounted payoff differences.  A price is
+ * e^{-rT} * S0 * (sum of level means).
+ *
+ * Conventions.  All structs are plain data, caller-owned, and begin with
+ * struct_size (set it to sizeof(the struct)); the library copies what it keeps
+ * before returning.  Pointers documented as "device" are HIP device addresses on
+ * the context's device; all others are host addresses.  No call throws; every
+ * call returns an mlmc_status and, on a context, leaves a message readable with
+ * mlmc_last_error.  MLMC_E_DEVICE poisons the context: every later call on it
+ * returns MLMC_E_DEVICE.
+ */
+#ifndef MLMC_H
+#define MLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLMC_ABI_VERSION 1
+#define MLMC_MAX_LEVELS 21      /* levels 0..20: h = 2^-l T (Section 2.1) */
+
+typedef enum mlmc_status {
+    MLMC_OK = 0,
+    MLMC_PENDING = 1,           /* mlmc_poll: request still running */
+    MLMC_E_INVALID = -1,        /* an argument failed validation */
+    MLMC_E_NOMEM = -2,          /* workspace (the HBM budget) too small */
+    MLMC_E_DEVICE = -3,         /* a HIP call failed; the context is poisoned */
+    MLMC_E_OVERFLOW = -4,       /* fixed-point saturation with strict overflow */
+    MLMC_E_BUSY = -5,           /* server not running / already running */
+    MLMC_E_TIMEOUT = -6,        /* deadline passed */
+    MLMC_E_UNKNOWN_TICKET = -7, /* mlmc_poll: no such ticket */
+    MLMC_E_VERSION = -8         /* struct_size does not match this library */
+} mlmc_status;
+
+/* Time-stepping scheme: Euler-Maruyama (Section 2.1, Algorithm 1) or Milstein. */
+enum { MLMC_EULER = 0, MLMC_MILSTEIN = 1 };
+
+/* Payoffs (bit positions of mlmc_problem.payoff_mask).  The paper prices the
+ * European call (Section 4.4); the others are evaluated on the same grid:
+ *   FORWARD  X_N (a test functional)
+ *   EURO     max(X_N - k, 0)
+ *   ASIAN    max(A - k, 0), A = (1/N) sum_{n<N} (X_n + X_{n+1}) / 2
+ *   BARRIER  max(X_N - k, 0) if min_{0<=n<=N} X_n > b, else 0 (down-and-out)
+ *   DIGITAL  k if X_N > k else 0 (cash-or-nothing paying K)
+ * with k = K / S0, b = barrier / S0, on each path's own grid. */
+enum { MLMC_PAY_FORWARD = 0, MLMC_PAY_EURO = 1, MLMC_PAY_ASIAN = 2,
+       MLMC_PAY_BARRIER = 3, MLMC_PAY_DIGITAL = 4, MLMC_NPAYOFF = 5 };
+
+/* Arithmetic of a path generator. */
+enum { MLMC_ARITH_FP64 = 0, MLMC_ARITH_FP32 = 1, MLMC_ARITH_FP16 = 2, MLMC_ARITH_FIXED = 3 };
+
+/* Estimators (Section 2.2): PLAIN samples dP_l with exact normals; APPROX
+ * samples the low-precision dP~_l with table normals; CORR samples
+ * dP_l - dP~_l with both sides driven by the same uniform integers. */
+enum { MLMC_EST_PLAIN = 0, MLMC_EST_APPROX = 1, MLMC_EST_CORR = 2 };
+
+/* Fixed-point variables of the low-precision step (Algorithm 1; the Milstein
+ * step adds zsq = Z*Z, zm1 = zsq - 1, mul3 = con3*zm1, sum2 = sum1 + mul3 with
+ * con3 = sigma^2 h / 2, and mul2 = X * sum2).  Index into word_bits/frac_bits. */
+enum { MLMC_V_X = 0, MLMC_V_CON1, MLMC_V_CON2, MLMC_V_CON3, MLMC_V_Z, MLMC_V_MUL1,
+       MLMC_V_SUM1, MLMC_V_ZSQ, MLMC_V_ZM1, MLMC_V_MUL3, MLMC_V_SUM2, MLMC_V_MUL2,
+       MLMC_NVARS };
+
+/* The option: GBM dS = r S dt + sigma S dW (Section 2.1, Algorithm 1).
+ * Validation: S0, K, sigma, T > 0; r >= 0; barrier < S0 when the barrier payoff
+ * is requested; payoff_mask non-zero with bits < MLMC_NPAYOFF. */
+typedef struct mlmc_problem {
+    uint32_t struct_size;
+    int32_t scheme;             /* MLMC_EULER | MLMC_MILSTEIN */
+    uint32_t payoff_mask;       /* 1 << MLMC_PAY_* ; several payoffs share paths */
+    int32_t reserved;
+    double S0, K, r, sigma, T;
+    double barrier;             /* down-and-out level B (price units) */
+} mlmc_problem;
+
+/* Arithmetic of the low-precision (APPROX, and approx side of CORR) generator,
+ * or of the PLAIN generator.
+ *   arith        PLAIN: FP64 or FP32 (exact normals in that precision).
+ *                APPROX/CORR: FP32, FP16 or FIXED with Method-1 table normals;
+ *                the exact side of CORR is always FP64 with FP64 normals.
+ *   table_bits   q, 1..12: table of 2^q interval means indexed by the top q bits
+ *                of the 32-bit uniform (Section 3.1, d = q).
+ *   packed       APPROX only: take floor(32/q) q-bit indices per 32-bit word
+ *                instead of one (the law of each index is the same).
+ *   word_bits,   FIXED only, per variable (MLMC_V_*): two's-complement word w
+ *   frac_bits    (2..32) and fractional bits f (0..62): value n 2^-f (Section 4.1,
+ *                w = d + 1, f = d - e).  Every operation is rounded once to the
+ *                destination's f, to nearest with ties toward +infinity, then
+ *                saturated to w bits (saturations are counted).  The table entries
+ *                use Z's format; the coarse sum of two normals keeps Z's f with one
+ *                more integer bit; constants and k, b are quantised exactly from
+ *                their FP64 values (con1 = r h, con2 = sigma * sqrt(h),
+ *                con3 = ((0.5 * sigma) * sigma) * h, k = K / S0, b = B / S0). */
+typedef struct mlmc_precision {
+    uint32_t struct_size;
+    int32_t arith;
+    int32_t table_bits;
+    int32_t packed;
+    int32_t word_bits[MLMC_NVARS];
+    int32_t frac_bits[MLMC_NVARS];
+} mlmc_precision;
+
+/* Sums of one (level, estimator, payoff) over a set of paths (Section 2.1:
+ * the per-level Monte Carlo estimator).  Y is the estimator's sample in
+ * normalised units.  sum1/sum2 are FP64 sums of Y and Y^2.  For FIXED APPROX,
+ * Y is an integer multiple of 2^-f_X and isum1 (int64) and isum2 (unsigned
+ * 128-bit, lo/hi) are its exact integer sums; the FP64 view is filled too.
+ * For CORR, esum1/esum2 are FP64 sums of the exact side's dP_l (for V_l). */
+typedef struct mlmc_sums {
+    uint64_t n;
+    double sum1, sum2;
+    int64_t isum1;
+    uint64_t isum2_lo, isum2_hi;
+    double esum1, esum2;
+    uint64_t saturations;       /* FIXED: saturated operations over all paths */
+    uint64_t nonfinite;         /* paths whose Y was not finite */
+} mlmc_sums;
+
+/* One record per path of a debug dump (mlmc_level_sums' debug_paths). */
+typedef struct mlmc_path_record {
+    double Y[MLMC_NPAYOFF];          /* estimator sample per payoff (0 if not asked) */
+    int64_t Yraw[MLMC_NPAYOFF];      /* approx side dP~: integer (FIXED) or the FP64
+                                        bit pattern of the float value */
+    double XN_exact, XcN_exact;      /* fine / coarse terminal values, exact side */
+    double XN_approx, XcN_approx;    /* approx side as FP64 (FIXED: n 2^-f_X) */
+    int64_t XN_raw, XcN_raw;         /* FIXED approx side: the integers n */
+    uint32_t first_word;             /* the 32-bit word holding fine step 0's uniform */
+    uint32_t first_index;            /* table index of fine step 0 */
+    uint32_t saturations;
+    uint32_t reserved;
+} mlmc_path_record;
+
+typedef struct mlmc_context mlmc_context;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.
+ * workspace: device buffer of workspace_bytes bytes that the context
+ * sub-allocates for tables, work lists and sums; it is the context's HBM budget
+ * (MLMC_E_NOMEM when a call needs more).  The caller owns it and keeps it alive
+ * until mlmc_context_destroy.  NULL asks the library to allocate workspace_bytes
+ * itself (freed at destroy).  stream: the hipStream_t every launch goes to (NULL:
+ * the null stream).  Errors: MLMC_E_INVALID (bad device, size < 1 MiB),
+ * MLMC_E_DEVICE (HIP failure). */
+mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t workspace_bytes,
+                                void* stream, mlmc_context** out);
+void mlmc_context_destroy(mlmc_context* ctx);
+const char* mlmc_last_error(const mlmc_context* ctx);
+const char* mlmc_status_string(int32_t status);
+int32_t mlmc_abi_version(void);
+
+/* --------------------------------------------------------------- level sums */
+
+/* Sums of one level's estimator over paths [path_offset, path_offset + n_paths)
+ * (Section 2.1 per-level estimator; Section 2.2 for APPROX/CORR).
+ * level: 0..20, h = 2^-level T; level 0 has no coarse path (P_{-1} = 0).
+ * seed, option_id: key and counter word of the uniform stream; path i, fine
+ * step n uses stream position i 2^level + n (see mlmc_stream_word).
+ * out: host array of popcount(payoff_mask) mlmc_sums, in increasing payoff
+ * order.  debug_paths: NULL or a device array of n_paths mlmc_path_record
+ * (same kernel; each record written once).
+ * Synchronous on the context's stream.  Errors: MLMC_E_INVALID (validation, see
+ * mlmc_problem / mlmc_precision; n_paths >= 1; path_offset + n_paths <= 2^40),
+ * MLMC_E_NOMEM, MLMC_E_DEVICE. */
+mlmc_status mlmc_level_sums(mlmc_context* ctx, const mlmc_problem* prob, int32_t level,
+                            uint64_t n_paths, uint64_t path_offset,
+                            const mlmc_precision* prec, int32_t estimator, uint64_t seed,
+                            uint32_t option_id, mlmc_sums* out, void* debug_paths);
+
+/* Many level sums in one launch sequence (one persistent kernel per estimator /
+ * arithmetic class over a ragged list of tiles, then one fixed-order reduction):
+ * e.g. every (level, estimator) of a nested MLMC estimate with its own N_l
+ * (Section 2.2).  Each work's sums equal those of mlmc_level_sums on the same
+ * arguments.  works: host array; each out points at popcount(payoff_mask) sums.
+ * Errors as mlmc_level_sums (the index of a failing work is in the message). */
+typedef struct mlmc_level_work {
+    uint32_t struct_size;
+    int32_t level;
+    int32_t estimator;
+    uint32_t option_id;
+    uint64_t n_paths, path_offset, seed;
+    const mlmc_problem* prob;
+    const mlmc_precision* prec;
+    mlmc_sums* out;
+} mlmc_level_work;
+
+mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works);
+
+/* Kernel timing.  With timing on, every path-kernel launch is bracketed by HIP
+ * events on the context's stream; per kernel class the library accumulates the
+ * launches, the summed event time and the fine path-steps processed. */
+typedef struct mlmc_kernel_stat {
+    int32_t estimator, arith, scheme, fields;  /* fields: indices per 32-bit word */
+    int32_t payoffs, track, pad0, pad1;
+    uint64_t launches;
+    double ms;                                 /* summed event time */
+    uint64_t path_steps;                       /* fine path-steps (paths * 2^level) */
+} mlmc_kernel_stat;
+
+mlmc_status mlmc_set_timing(mlmc_context* ctx, int32_t on);  /* also clears the stats */
+/* Copies up to max stats into out (host); *n receives the number available. */
+mlmc_status mlmc_kernel_stats(mlmc_context* ctx, mlmc_kernel_stat* out, uint32_t max, uint32_t* n);
+
+/* ----------------------------------------------------------- MLMC estimates */
+
+/* On-line nested MLMC (Sections 2.1, 2.2 and 6): pilot samples on levels
+ * 0..L_min, optimal allocation N_l = ceil(theta^-1 eps^-2 sqrt(V_l/C_l) Lambda)
+ * (plain) or N~_l, N^D_l with the common Lambda (nested), sweeps of the missing
+ * samples, then a bias test |mean_L| / (2^alpha - 1) > sqrt(1 - theta) eps that
+ * adds level L+1 up to L_max.  Costs are the deterministic model
+ * C_l = 2^l c_estimator (Section 5: C_l ~ 2^l C_RNG).  eps_units 0: eps on the
+ * price / S0; 1: eps in price units. */
+typedef struct mlmc_run_config {
+    uint32_t struct_size;
+    int32_t nested;             /* 1: APPROX + CORR per level; 0: PLAIN */
+    int32_t eps_units;          /* 0 normalised, 1 absolute */
+    int32_t L_min, L_max;       /* 0 <= L_min <= L_max <= 20 */
+    int32_t plain_arith;        /* PLAIN generator: FP64 or FP32 */
+    double eps, theta;          /* eps > 0, 0 < theta <= 1 */
+    uint64_t n_pilot;           /* >= 2 */
+    double cost_plain, cost_approx, cost_corr;   /* cost per fine path-step (> 0) */
+    mlmc_precision prec[MLMC_MAX_LEVELS];        /* approx side per level (nested) */
+} mlmc_run_config;
+
+typedef struct mlmc_level_stats {
+    uint64_t n[3];              /* samples per estimator (PLAIN, APPROX, CORR) */
+    double mean[3], var[3];     /* normalised level mean and variance (R9) */
+} mlmc_level_stats;
+
+typedef struct mlmc_result {
+    uint32_t struct_size;
+    int32_t status;
+    int32_t L;                  /* finest level used */
+    int32_t sweeps;
+    double estimate;            /* e^{-rT} S0 sum_l (means) */
+    double variance;            /* (e^{-rT} S0)^2 sum_l var / n */
+    double seconds;             /* wall time of the estimate */
+    uint64_t path_steps;        /* fine path-steps generated, all estimators */
+    uint64_t saturations;
+    mlmc_level_stats level[MLMC_MAX_LEVELS];
+} mlmc_result;
+
+/* One option, one payoff (single bit of payoff_mask).  Errors as
+ * mlmc_level_sums plus MLMC_E_INVALID for the run config. */
+mlmc_status mlmc_estimate(mlmc_context* ctx, const mlmc_problem* prob,
+                          const mlmc_run_config* cfg, uint64_t seed, uint32_t option_id,
+                          mlmc_result* out);
+
+/* n options at once (option i uses option_id i and payoff bit of probs[i]); each
+ * sweep of all options runs as one persistent launch over a ragged work list.
+ * Each option's result equals that of mlmc_estimate alone with the same
+ * (seed, option_id). */
+mlmc_status mlmc_estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* probs,
+                                const mlmc_run_config* cfg, uint64_t seed,
+                                mlmc_result* out);
+
+/* ------------------------------------------------------------------ serving */
+
+/* Continuous batching.  mlmc_server_start launches a scheduler thread on the
+ * context.  Requests are admitted while their device state fits in the
+ * workspace (the HBM budget) and a slot is free; every sweep gathers the pending
+ * work of all admitted requests into one launch, so requests that arrive while
+ * others run join the next sweep.  A request's result is the same as
+ * mlmc_estimate with its (seed, option_id) and run config. */
+typedef struct mlmc_server_config {
+    uint32_t struct_size;
+    uint32_t max_active;        /* slots: requests on the device at once (>= 1) */
+    mlmc_run_config run;        /* template; eps and nesting come from each request */
+} mlmc_server_config;
+
+typedef struct mlmc_request {
+    uint32_t struct_size;
+    uint32_t option_id;
+    mlmc_problem problem;       /* one payoff bit */
+    double eps;                 /* this request's eps (units of run.eps_units) */
+    uint64_t seed;
+    int32_t nested;
+    int32_t reserved;
+} mlmc_request;
+
+mlmc_status mlmc_server_start(mlmc_context* ctx, const mlmc_server_config* cfg);
+/* Copies the request; returns a ticket.  Thread-safe. */
+mlmc_status mlmc_submit(mlmc_context* ctx, const mlmc_request* req, uint64_t* ticket);
+/* MLMC_PENDING until done, then MLMC_OK with the result (once).  Thread-safe. */
+mlmc_status mlmc_poll(mlmc_context* ctx, uint64_t ticket, mlmc_result* out);
+/* Finishes admitted work, stops the thread. */
+mlmc_status mlmc_server_stop(mlmc_context* ctx);
+
+/* ------------------------------------------------- host-side helpers (no GPU) */
+
+/* Method-1 table (Section 3.1): T_q[k] = 2^q (phi(Phi^-1(k 2^-q)) -
+ * phi(Phi^-1((k+1) 2^-q))), the mean of Phi^-1 over interval k, rounded to
+ * nearest in the target format.  arith FP64 -> double[2^q]; FP32 -> float[2^q];
+ * FP16 -> uint16_t[2^q] (binary16 bits); FIXED -> int32_t[2^q] with frac_bits
+ * fractional bits.  out: host buffer.  Errors: MLMC_E_INVALID (q outside 1..16). */
+mlmc_status mlmc_build_table(int32_t q, int32_t arith, int32_t frac_bits, void* out);
+
+/* The 32-bit uniform word at stream position `word_index` (Philox4x32-10,
+ * Salmon et al. 2011; counter (b mod 2^32, b div 2^32, level | estimator << 8,
+ * option_id) for block b = word_index / 4, key = seed) -- host evaluation, for
+ * checking.  out: host array of `count` words starting at word_index. */
+mlmc_status mlmc_stream_words(uint64_t seed, uint32_t option_id, int32_t level,
+                              int32_t estimator, uint64_t word_index, uint64_t count,
+                              uint32_t* out);
+
+/* Argument validation as performed by mlmc_level_sums (no device needed). */
+mlmc_status mlmc_validate(const mlmc_problem* prob, int32_t level, uint64_t n_paths,
+                          uint64_t path_offset, const mlmc_precision* prec,
+                          int32_t estimator);
+
+/* The kernels' per-path code compiled for the host, run on paths
+ * [path_offset, path_offset + n_paths) with n_paths <= 65536: the same
+ * arithmetic and per-path records as mlmc_level_sums (sums are added in path
+ * order rather than the kernels' tree order).  A checker of the kernel
+ * arithmetic on machines without a GPU; no other entry point calls it.
+ * out: as mlmc_level_sums; records: host array of n_paths records or NULL.
+ * Errors: MLMC_E_INVALID (validation, n_paths > 65536), MLMC_E_OVERFLOW. */
+mlmc_status mlmc_check_paths_host(const mlmc_problem* prob, int32_t level, uint64_t n_paths,
+                                  uint64_t path_offset, const mlmc_precision* prec,
+                                  int32_t estimator, uint64_t seed, uint32_t option_id,
+                                  mlmc_sums* out, mlmc_path_record* records);
+
+/* Sample allocation (Section 2.1 / 2.2) as used by the drivers:
+ * N_i = ceil(theta^-1 eps2^-1 sqrt(V_i / C_i) sum_j sqrt(V_j C_j)) over the m
+ * (level, estimator) pairs given.  out: host uint64_t[m]. */
+mlmc_status mlmc_allocate(uint32_t m, const double* V, const double* C, double eps2,
+                          double theta, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLMC_H */

@@ -380,8 +380,10 @@ def simulate(prob: Problem, level: int, paths, prec: Precision, estimator: int,
         out[name] = res
     if exact_side is not None:
         out["XN_exact"], out["XcN_exact"] = exact_side.Xf, exact_side.Xc
+        out["min_exact"], out["minc_exact"] = exact_side.min_f, exact_side.min_c
     if approx_side is not None:
         out["XN_approx"], out["XcN_approx"] = approx_side.Xf, approx_side.Xc
+        out["min_approx"], out["minc_approx"] = approx_side.min_f, approx_side.min_c
         sat = approx_side.side.sat
         out["sat"] = np.zeros(n, np.int64) if sat is None else sat
     return out

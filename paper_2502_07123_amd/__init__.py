@@ -1,0 +1,186 @@
+"""Nested multilevel Monte Carlo on MI355X (gfx950).
+
+The hot path of Haas & Giles' nested MLMC method -- coupled fine/coarse GBM
+paths from counter-based uniforms, exact or Method-1 table normals, FP64 / FP32 /
+per-variable fixed-point arithmetic, level sums of payoff differences for the
+plain and the two nested estimators -- runs in HIP kernels behind the C ABI of
+include/mlmc.h.  This module is the Python binding: argument marshalling, plus
+PyTorch for the device workspace and the stream.
+"""
+import ctypes as C
+
+import numpy as np
+
+from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, PAYOFFS, RECORD_DTYPE, VARS, KernelStat, LevelWork,
+                   MlmcError, Problem, Precision, Request, Result, RunConfig, ServerConfig, Sums,
+                   check, lib, make_precision, make_problem, make_run_config)
+
+__all__ = ["Context", "make_problem", "make_precision", "make_run_config", "build_table",
+           "stream_words", "check_paths_host", "allocate", "validate", "MlmcError",
+           "EST_PLAIN", "EST_APPROX", "EST_CORR", "PAYOFFS", "VARS", "RECORD_DTYPE"]
+
+
+def _payoff_names(problem):
+    return [p for i, p in enumerate(PAYOFFS) if (problem.payoff_mask >> i) & 1]
+
+
+class Context:
+    """A library context on one GPU: workspace (the HBM budget) allocated by
+    PyTorch, launches on the given torch stream (default: the current stream)."""
+
+    def __init__(self, device=0, workspace_bytes=256 << 20, stream=None):
+        import torch
+        self.device = device
+        self._ws = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        check(lib().mlmc_context_create(device, C.c_void_p(self._ws.data_ptr()), int(workspace_bytes),
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mlmc_context_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return lib().mlmc_last_error(self.h).decode()
+
+    def level_sums(self, problem, level, n_paths, path_offset, prec, estimator, seed, option=0,
+                   debug=False):
+        """Sums per payoff (dicts, in payoff order) and, with debug, per-path records
+        (numpy structured array of RECORD_DTYPE)."""
+        import torch
+        names = _payoff_names(problem)
+        out = (Sums * len(names))()
+        rec = None
+        if debug:
+            rec = torch.zeros(int(n_paths) * RECORD_DTYPE.itemsize, dtype=torch.uint8,
+                              device=f"cuda:{self.device}")
+        st = lib().mlmc_level_sums(self.h, C.byref(problem), level, int(n_paths), int(path_offset),
+                                   C.byref(prec), estimator, int(seed), option, out,
+                                   C.c_void_p(rec.data_ptr()) if debug else None)
+        check(st, self.h)
+        sums = {n: out[i].as_dict() for i, n in enumerate(names)}
+        if not debug:
+            return sums
+        return sums, np.frombuffer(rec.cpu().numpy().tobytes(), dtype=RECORD_DTYPE)
+
+    def level_sums_batch(self, items):
+        """items: list of (problem, level, n_paths, path_offset, prec, estimator, seed, option).
+        One launch sequence; returns one {payoff: sums} dict per item."""
+        n = len(items)
+        keep = []
+        works = (LevelWork * n)()
+        outs = []
+        for i, (prob, level, npaths, off, prec, est, seed, opt) in enumerate(items):
+            names = _payoff_names(prob)
+            out = (Sums * len(names))()
+            outs.append((names, out))
+            keep.append((prob, prec))
+            works[i] = LevelWork(C.sizeof(LevelWork), level, est, opt, int(npaths), int(off),
+                                 int(seed), C.pointer(prob), C.pointer(prec),
+                                 C.cast(out, C.POINTER(Sums)))
+        check(lib().mlmc_level_sums_batch(self.h, n, works), self.h)
+        return [{nm: out[j].as_dict() for j, nm in enumerate(names)} for names, out in outs]
+
+    def set_timing(self, on=True):
+        check(lib().mlmc_set_timing(self.h, 1 if on else 0), self.h)
+
+    def kernel_stats(self):
+        cnt = C.c_uint32()
+        check(lib().mlmc_kernel_stats(self.h, None, 0, C.byref(cnt)), self.h)
+        arr = (KernelStat * max(cnt.value, 1))()
+        check(lib().mlmc_kernel_stats(self.h, arr, cnt.value, C.byref(cnt)), self.h)
+        return [arr[i].as_dict() for i in range(cnt.value)]
+
+    def estimate(self, problem, cfg, seed, option=0):
+        r = Result()
+        r.struct_size = C.sizeof(Result)
+        check(lib().mlmc_estimate(self.h, C.byref(problem), C.byref(cfg), int(seed), option,
+                                  C.byref(r)), self.h)
+        return r.as_dict()
+
+    def estimate_batch(self, problems, cfg, seed):
+        n = len(problems)
+        arr = (Problem * n)(*problems)
+        res = (Result * n)()
+        check(lib().mlmc_estimate_batch(self.h, n, arr, C.byref(cfg), int(seed), res), self.h)
+        return [res[i].as_dict() for i in range(n)]
+
+    # ---- serving
+    def server_start(self, run_cfg, max_active=256):
+        sc = ServerConfig(C.sizeof(ServerConfig), max_active, run_cfg)
+        check(lib().mlmc_server_start(self.h, C.byref(sc)), self.h)
+
+    def submit(self, problem, eps, seed, option=0, nested=True):
+        req = Request(C.sizeof(Request), option, problem, eps, int(seed), 1 if nested else 0, 0)
+        t = C.c_uint64()
+        check(lib().mlmc_submit(self.h, C.byref(req), C.byref(t)), self.h)
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending, else the result dict."""
+        r = Result()
+        st = lib().mlmc_poll(self.h, int(ticket), C.byref(r))
+        if st == 1:
+            return None
+        check(st, self.h)
+        return r.as_dict()
+
+    def server_stop(self):
+        check(lib().mlmc_server_stop(self.h), self.h)
+
+
+# ---------------------------------------------------------- host-side helpers
+def build_table(q, arith="fp32", frac_bits=0):
+    dt = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "fixed": np.int32}[arith]
+    out = np.zeros(1 << q, dtype=dt)
+    check(lib().mlmc_build_table(q, ARITH[arith], frac_bits, out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def stream_words(seed, option, level, estimator, word_index, count):
+    out = np.zeros(int(count), dtype=np.uint32)
+    check(lib().mlmc_stream_words(int(seed), option, level, estimator, int(word_index), int(count),
+                                  out.ctypes.data_as(C.POINTER(C.c_uint32))))
+    return out
+
+
+def check_paths_host(problem, level, n_paths, path_offset, prec, estimator, seed, option=0):
+    """The kernels' per-path code run on the host (a checker; n_paths <= 65536)."""
+    names = _payoff_names(problem)
+    out = (Sums * len(names))()
+    rec = np.zeros(int(n_paths), dtype=RECORD_DTYPE)
+    check(lib().mlmc_check_paths_host(C.byref(problem), level, int(n_paths), int(path_offset),
+                                      C.byref(prec), estimator, int(seed), option, out,
+                                      rec.ctypes.data_as(C.c_void_p)))
+    return {n: out[i].as_dict() for i, n in enumerate(names)}, rec
+
+
+def allocate(V, Cost, eps2, theta=1.0):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    Cc = np.ascontiguousarray(Cost, dtype=np.float64)
+    out = np.zeros(V.size, dtype=np.uint64)
+    check(lib().mlmc_allocate(V.size, V.ctypes.data_as(C.POINTER(C.c_double)),
+                              Cc.ctypes.data_as(C.POINTER(C.c_double)), eps2, theta,
+                              out.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return out
+
+
+def validate(problem, level, n_paths, path_offset, prec, estimator):
+    """The library's status code for these arguments (0 = valid)."""
+    return lib().mlmc_validate(C.byref(problem), level, int(n_paths), int(path_offset),
+                               C.byref(prec), estimator)

@@ -1,0 +1,80 @@
+// Data shared by the host runtime and the kernels (internal; not part of the ABI).
+//
+// A launch processes a list of tiles.  A tile is a contiguous range of "path
+// groups" of one work item; a work item is one (option, level, estimator) path
+// range [path_begin, path_end); a level entry holds everything the path code needs
+// for one (option parameters, level, precision).  A path group is the set of paths
+// whose uniforms come from whole Philox blocks: with WPB normals per block and
+// N = 2^level steps per path, a group holds max(1, WPB / N) paths and
+// max(N, WPB) consecutive stream positions.
+#pragma once
+#include <cstdint>
+
+#include "device/fixed.hpp"
+#include "../../include/mlmc.h"
+
+namespace mlmc {
+
+constexpr int NPAY = MLMC_NPAYOFF;
+
+// Stream positions of one path group: lcm(2^level, wpb), so that a group holds
+// whole paths and whole Philox blocks (wpb = 4 * indices per word).
+__host__ __device__ __forceinline__ uint64_t group_span(int level, uint32_t wpb) {
+    const uint64_t N = uint64_t(1) << level;
+    uint64_t a = N, b = wpb;
+    while (b) { const uint64_t t = a % b; a = b; b = t; }
+    return N / a * wpb;
+}
+
+struct LevelDev {
+    // exact side (FP64 constants of the level)
+    double con1, con1c, con2, con3, k, b;
+    // FP32 side (constants rounded to FP32; f2con3 = 2 con3 for the coarse cross term)
+    float fcon1, fcon1c, fcon2, fcon3, fk, fb, f2con3, fpad;
+    // fixed-point side
+    int64_t icon1, icon1c, icon2, icon3, ik, ib;
+    int64_t izm_c2;           // the constant 2 in zsq's format
+    int32_t fX, wX;
+    FxOp op_mul2, op_addX, op_mul1, op_sum1, op_zsq, op_zm1, op_mul3, op_sum2;
+    // structure
+    int32_t level, scheme;
+    uint32_t payoff_mask;
+    int32_t payoff_single;    // payoff id of a one-payoff launch
+    int32_t q;
+    uint32_t table_entries;   // 2^q
+    uint32_t table_off;       // byte offset of the step table in the table arena
+    uint32_t table_bytes;
+};
+
+struct WorkDev {
+    uint32_t lvl;             // index of its LevelDev
+    uint32_t c2, c3;          // counter words: level | estimator << 8, option
+    uint32_t k0, k1;          // key = seed
+    uint32_t sums;            // index of its accumulated sums
+    uint64_t path_begin, path_end;
+    uint64_t debug;           // device address of mlmc_path_record[path_end - path_begin] or 0
+};
+
+struct TileDev {
+    uint32_t work;
+    uint32_t slot;
+    uint64_t group_begin;
+    uint32_t n_groups;
+    uint32_t pad;
+};
+
+// Partial or accumulated sums of one work item (all payoffs).
+struct SlotDev {
+    double s1[NPAY], s2[NPAY], e1[NPAY], e2[NPAY];
+    int64_t i1[NPAY];
+    uint64_t i2lo[NPAY], i2hi[NPAY];
+    uint64_t n, sat, nonfinite, pad;
+};
+
+struct ReduceDev {
+    uint32_t slot_begin, slot_end;   // this work item's tile slots
+    uint32_t sums;                   // destination
+    uint32_t accumulate;             // add to the destination (1) or overwrite (0)
+};
+
+}  // namespace mlmc

@@ -1,0 +1,428 @@
+// Per-thread work of the path kernels: one "path group" of coupled fine/coarse
+// GBM paths (Section 2.1; Algorithm 1), its payoffs and the estimator samples
+// (Section 2.2), accumulated into per-thread sums.
+//
+// Steps.  Exact side (FP64, or FP32 for the plain-FP32 estimator):
+//   s = con1 + con2 Z (+ con3 (Z^2 - 1), Milstein),  X <- X + X s
+//   coarse, once per fine pair: Zs = Z_2m + Z_2m+1, s = con1c + con2 Zs
+//   (+ con3 (Zs^2 - 2)), Xc <- Xc + Xc s  (drift and volatility frozen over the
+//   pair, Section 2.1).
+// Low-precision side with Method-1 normals (Section 3.1).  The table holds, per
+// interval k, (Z~_k, s_k) with s_k the step multiplier the arithmetic would form
+// from Z~_k -- a function of k alone -- so the fine step is X <- X + X s_k:
+//   FP32:  s_k is the level's s from Z~_k rounded once to FP32; the coarse
+//          multiplier is s_a + s_b (+ 2 con3 Z~_a Z~_b), which equals the coarse s of
+//          Zs = Z~_a + Z~_b in exact arithmetic.  Paths agree with the per-operation
+//          FP32 reference to rounding (about 1e-6 relative).
+//   FIXED: s_k is sum1 (Euler) or sum2 (Milstein) of Algorithm 1's chain in the
+//          per-variable formats, built on the host with the same rounding; the
+//          coarse step runs the whole chain on Zs.  Bit-exact by construction.
+// Uniforms: Philox block b of the stream gives 4 words; unpacked, each word is one
+// step (index = top q bits, exact normal from the whole word); packed (APPROX), a
+// word holds F = floor(32/q) indices, field j = bits [32-q(j+1), 32-qj).
+#pragma once
+#include <cmath>
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+#include "../common.hpp"
+#include "fixed.hpp"
+#include "norminv.hpp"
+#include "philox.hpp"
+
+namespace mlmc {
+
+template <int NP>
+struct Acc {
+    double s1[NP], s2[NP], e1[NP], e2[NP];
+    int64_t i1[NP];
+    uint64_t i2lo[NP], i2hi[NP];
+    uint32_t n, sat, nonfinite;
+};
+
+template <int NP>
+__host__ __device__ __forceinline__ void acc_zero(Acc<NP>& a) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        a.s1[p] = a.s2[p] = a.e1[p] = a.e2[p] = 0.0;
+        a.i1[p] = 0;
+        a.i2lo[p] = a.i2hi[p] = 0;
+    }
+    a.n = a.sat = a.nonfinite = 0;
+}
+
+// ----------------------------------------------------------------- float sides
+template <typename T>
+struct FSide {
+    T xf, xc, af, ac, mf, mc, zp, sp;
+
+    __host__ __device__ __forceinline__ void init() {
+        xf = xc = mf = mc = T(1);
+        af = ac = T(0);
+        zp = sp = T(0);
+    }
+    __host__ __device__ __forceinline__ void track_f(bool on) {
+        if (on) { af = af + xf; mf = xf < mf ? xf : mf; }
+    }
+    __host__ __device__ __forceinline__ void track_c(bool on) {
+        if (on) { ac = ac + xc; mc = xc < mc ? xc : mc; }
+    }
+    // payoff p of the fine (coarse) path with log2 of its step count m
+    __host__ __device__ __forceinline__ T payoff(int p, bool fine, int m, T k, T b) const {
+#pragma clang fp contract(off)
+        const T X = fine ? xf : xc;
+        const T zero = T(0);
+        switch (p) {
+            case MLMC_PAY_FORWARD: return X;
+            case MLMC_PAY_EURO: { const T d = X - k; return d > zero ? d : zero; }
+            case MLMC_PAY_ASIAN: {
+                T t = (fine ? af : ac) - T(0.5) * X;
+                t = t + T(0.5);                                  // + X_0 / 2, X_0 = 1
+                const T A = t * T(ldexp(1.0, -m));
+                const T d = A - k;
+                return d > zero ? d : zero;
+            }
+            case MLMC_PAY_BARRIER: {
+                const T d = X - k;
+                return ((fine ? mf : mc) > b && d > zero) ? d : zero;
+            }
+            default: return X > k ? k : zero;                    // digital
+        }
+    }
+};
+
+// exact-normal step in FP64 or FP32
+template <bool MIL>
+__host__ __device__ __forceinline__ void exact_step(FSide<double>& s, double Z, const LevelDev& L,
+                                                    bool coarse_on, bool odd, bool track) {
+    double t = fma(L.con2, Z, L.con1);
+    if (MIL) t = fma(L.con3, fma(Z, Z, -1.0), t);
+    s.xf = fma(s.xf, t, s.xf);
+    s.track_f(track);
+    if (coarse_on) {
+        if (!odd) {
+            s.zp = Z;
+        } else {
+            const double zs = s.zp + Z;
+            double tc = fma(L.con2, zs, L.con1c);
+            if (MIL) tc = fma(L.con3, fma(zs, zs, -2.0), tc);
+            s.xc = fma(s.xc, tc, s.xc);
+            s.track_c(track);
+        }
+    }
+}
+
+// FP32 steps follow Algorithm 1 operation by operation, each rounded to FP32 (no
+// fused multiply-add), so FP32 paths are reproducible bit for bit.
+// The multiplier of one step from a normal z: mul1 = con2 z, sum1 = con1 + mul1
+// (Milstein: zsq = z z, zm1 = zsq - c, mul3 = con3 zm1, sum2 = sum1 + mul3).
+template <bool MIL>
+__host__ __device__ __forceinline__ float multiplier32(float z, float con1, float con2, float con3,
+                                                       float c) {
+#pragma clang fp contract(off)
+    const float mul1 = con2 * z;
+    float s = con1 + mul1;
+    if (MIL) {
+        const float zsq = z * z;
+        const float zm1 = zsq - c;
+        const float mul3 = con3 * zm1;
+        s = s + mul3;
+    }
+    return s;
+}
+
+__host__ __device__ __forceinline__ float advance32(float x, float s) {
+#pragma clang fp contract(off)
+    const float mul2 = x * s;
+    return x + mul2;
+}
+
+template <bool MIL>
+__host__ __device__ __forceinline__ void exact_step(FSide<float>& s, float Z, const LevelDev& L,
+                                                    bool coarse_on, bool odd, bool track) {
+    s.xf = advance32(s.xf, multiplier32<MIL>(Z, L.fcon1, L.fcon2, L.fcon3, 1.0f));
+    s.track_f(track);
+    if (coarse_on) {
+        if (!odd) {
+            s.zp = Z;
+        } else {
+            const float zs = s.zp + Z;
+            s.xc = advance32(s.xc, multiplier32<MIL>(zs, L.fcon1c, L.fcon2, L.fcon3, 2.0f));
+            s.track_c(track);
+        }
+    }
+}
+
+// table step, FP32 low-precision side; entry = (Z~_k, s_k) with s_k the fine
+// multiplier of Z~_k (multiplier32 evaluated on the host)
+template <bool MIL>
+__host__ __device__ __forceinline__ void table_step(FSide<float>& s, float z, float sk,
+                                                    const LevelDev& L, bool coarse_on, bool odd,
+                                                    bool track) {
+    s.xf = advance32(s.xf, sk);
+    s.track_f(track);
+    if (coarse_on) {
+        if (!odd) {
+            s.zp = z;
+        } else {
+            const float zs = s.zp + z;
+            s.xc = advance32(s.xc, multiplier32<MIL>(zs, L.fcon1c, L.fcon2, L.fcon3, 2.0f));
+            s.track_c(track);
+        }
+    }
+}
+
+// ----------------------------------------------------------------- fixed side
+struct XSide {
+    int64_t xf, xc, af, ac, mf, mc, zp;
+    uint32_t nsat;
+
+    __host__ __device__ __forceinline__ void init(const LevelDev& L) {
+        xf = xc = mf = mc = int64_t(1) << L.fX;
+        af = ac = 0;
+        zp = 0;
+        nsat = 0;
+    }
+    __host__ __device__ __forceinline__ int64_t payoff(int p, bool fine, int m,
+                                                       const LevelDev& L) {
+        const int64_t X = fine ? xf : xc;
+        switch (p) {
+            case MLMC_PAY_FORWARD: return X;
+            case MLMC_PAY_EURO: { const int64_t d = X - L.ik; return d > 0 ? d : 0; }
+            case MLMC_PAY_ASIAN: {
+                // 2 * trapezoid sum = 2 sum_{n=1..N} X_n - X_N + X_0, exact; / 2^(m+1)
+                const int64_t s2 = 2 * (fine ? af : ac) - X + (int64_t(1) << L.fX);
+                const int64_t A = fx_saturate(fx_round_shift(s2, m + 1), L.wX, nsat);
+                const int64_t d = A - L.ik;
+                return d > 0 ? d : 0;
+            }
+            case MLMC_PAY_BARRIER: {
+                const int64_t d = X - L.ik;
+                return ((fine ? mf : mc) > L.ib && d > 0) ? d : 0;
+            }
+            default: return X > L.ik ? L.ik : 0;
+        }
+    }
+};
+
+template <bool MIL>
+__host__ __device__ __forceinline__ void fixed_step(XSide& s, int64_t z, int64_t sk,
+                                                    const LevelDev& L, bool coarse_on, bool odd,
+                                                    bool track) {
+    const int64_t m2 = fx_mul(s.xf, sk, L.op_mul2, s.nsat);
+    s.xf = fx_add(s.xf, m2, L.op_addX, s.nsat);
+    if (track) { s.af += s.xf; s.mf = s.xf < s.mf ? s.xf : s.mf; }
+    if (coarse_on) {
+        if (!odd) {
+            s.zp = z;
+        } else {
+            const int64_t zs = s.zp + z;                       // exact, one more integer bit
+            const int64_t m1 = fx_mul(L.icon2, zs, L.op_mul1, s.nsat);
+            int64_t sc = fx_add(L.icon1c, m1, L.op_sum1, s.nsat);
+            if (MIL) {
+                const int64_t zq = fx_mul(zs, zs, L.op_zsq, s.nsat);
+                const int64_t zm = fx_add(zq, -L.izm_c2, L.op_zm1, s.nsat);
+                const int64_t m3 = fx_mul(L.icon3, zm, L.op_mul3, s.nsat);
+                sc = fx_add(sc, m3, L.op_sum2, s.nsat);
+            }
+            const int64_t m2c = fx_mul(s.xc, sc, L.op_mul2, s.nsat);
+            s.xc = fx_add(s.xc, m2c, L.op_addX, s.nsat);
+            if (track) { s.ac += s.xc; s.mc = s.xc < s.mc ? s.xc : s.mc; }
+        }
+    }
+}
+
+// ------------------------------------------------------------- path kernel body
+// EST: MLMC_EST_*; ARITH: arithmetic of the table side (APPROX/CORR) or of the
+// plain side (PLAIN: FP64 or FP32); NP: 1 (payoff_single) or NPAY (payoff_mask);
+// TRACK: keep Asian sums and running minima; F: indices per word (1 = unpacked).
+template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
+struct PathBody {
+    static constexpr int WPB = 4 * F;                                  // normals per block
+    static constexpr int WPB_TZ = 2 + (F % 2 ? 0 : (F % 4 ? 1 : (F % 8 ? 2 : 3)));   // trailing zeros
+    static constexpr bool HAS_EXACT = EST != MLMC_EST_APPROX;
+    static constexpr bool HAS_TABLE = EST != MLMC_EST_PLAIN;
+    static constexpr bool FIXED = ARITH == MLMC_ARITH_FIXED;
+    static constexpr bool PLAIN32 = EST == MLMC_EST_PLAIN && ARITH == MLMC_ARITH_FP32;
+    // table entry: FP32 Euler needs only s_k; the others (Z~_k, s_k)
+    static constexpr bool TAB_PAIR = true;       // (Z~_k, s_k): the coarse chain needs Z~
+    static constexpr int TAB_BYTES = !HAS_TABLE ? 0 : 8;
+    using ExactT = typename std::conditional<PLAIN32, float, double>::type;
+
+    // tab: table of 2^q entries (LDS on the device, host memory in checks)
+    __host__ __device__ __forceinline__ static void run_group(const LevelDev& L, const WorkDev& W,
+                                                              uint64_t g, const void* tab,
+                                                              Acc<NP>& acc) {
+        const int lev = L.level;
+        // group = lcm(2^lev, WPB) stream positions (group_span): whole paths, whole blocks
+        const uint64_t S = (uint64_t(WPB) << lev) >> (lev < WPB_TZ ? lev : WPB_TZ);
+        const uint32_t nblk = static_cast<uint32_t>(S / WPB);
+        const uint64_t path0 = g * (S >> lev);
+        const bool coarse_on = lev >= 1;
+        const int q = L.q;
+        const uint32_t qmask = (1u << q) - 1u;
+        uint64_t blk = g * nblk;
+
+        FSide<ExactT> ex;
+        FSide<float> ap;
+        XSide ax;
+        uint32_t first_word = 0, first_index = 0;
+
+        for (uint32_t ib = 0; ib < nblk; ++ib, ++blk) {
+            u32x4 r = philox4x32_10(
+                u32x4{static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32), W.c2, W.c3},
+                W.k0, W.k1);
+            if (HAS_EXACT) {
+                // one word per step; a rolled loop keeps a single copy of the exact
+                // inverse normal (the words rotate through r.x)
+#pragma unroll 1
+                for (int wi = 0; wi < 4; ++wi) {
+                    const uint32_t J = r.x;
+                    r.x = r.y;
+                    r.y = r.z;
+                    r.z = r.w;
+                    step(L, W, tab, ib * 4u + wi, (wi & 1) != 0, J, 0, path0, ex, ap, ax,
+                         first_word, first_index, acc);
+                }
+            } else {
+                const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+                for (int wi = 0; wi < 4; ++wi) {
+#pragma unroll
+                    for (int fi = 0; fi < F; ++fi)
+                        step(L, W, tab, (ib * 4u + wi) * F + fi, ((wi * F + fi) & 1) != 0, wd[wi], fi,
+                             path0, ex, ap, ax, first_word, first_index, acc);
+                }
+            }
+        }
+    }
+
+    // Stream position sl of the group (odd = sl & 1, known at compile time when
+    // unrolled since 4F is even); J the word holding it, fi its field.
+    __host__ __device__ __forceinline__ static void step(
+        const LevelDev& L, const WorkDev& W, const void* tab, uint32_t sl, bool odd, uint32_t J,
+        int fi, uint64_t path0, FSide<ExactT>& ex, FSide<float>& ap, XSide& ax,
+        uint32_t& first_word, uint32_t& first_index, Acc<NP>& acc) {
+        const int lev = L.level;
+        const uint32_t N = 1u << lev;
+        const uint32_t n = sl & (N - 1u);
+        const bool coarse_on = lev >= 1;
+        const int q = L.q;
+        if (n == 0) {
+            if (HAS_EXACT) ex.init();
+            if (HAS_TABLE) { if (FIXED) ax.init(L); else ap.init(); }
+        }
+        uint32_t k = 0;
+        if (HAS_TABLE)
+            k = (F == 1) ? (J >> (32 - q)) : ((J >> (32 - q * (fi + 1))) & ((1u << q) - 1u));
+        if (n == 0) { first_word = J; first_index = k; }
+        if (HAS_EXACT) {
+            if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J), L, coarse_on, odd, TRACK);
+            else exact_step<MIL>(ex, norminv_f64(J), L, coarse_on, odd, TRACK);
+        }
+        if (HAS_TABLE) {
+            if (FIXED) {
+                const int2 e = static_cast<const int2*>(tab)[k];
+                fixed_step<MIL>(ax, e.x, e.y, L, coarse_on, odd, TRACK);
+            } else if (TAB_PAIR) {
+                const float2 e = static_cast<const float2*>(tab)[k];
+                table_step<MIL>(ap, e.x, e.y, L, coarse_on, odd, TRACK);
+            } else {
+                const float sk = static_cast<const float*>(tab)[k];
+                table_step<MIL>(ap, 0.0f, sk, L, coarse_on, odd, TRACK);
+            }
+        }
+        if (n == N - 1u) {
+            const uint64_t pidx = path0 + (sl >> lev);
+            if (pidx >= W.path_begin && pidx < W.path_end)
+                finish(L, W, pidx, ex, ap, ax, first_word, first_index, acc);
+        }
+    }
+
+    __host__ __device__ __forceinline__ static void finish(const LevelDev& L, const WorkDev& W,
+                                                           uint64_t pidx, const FSide<ExactT>& ex,
+                                                           const FSide<float>& ap, XSide& ax,
+                                                           uint32_t first_word,
+                                                           uint32_t first_index, Acc<NP>& acc) {
+        const int lev = L.level;
+        mlmc_path_record* rec =
+            W.debug ? reinterpret_cast<mlmc_path_record*>(W.debug) + (pidx - W.path_begin) : nullptr;
+        const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
+        const ExactT eb = PLAIN32 ? ExactT(L.fb) : ExactT(L.b);
+#pragma unroll
+        for (int slot = 0; slot < NP; ++slot) {
+            const int p = NP == 1 ? L.payoff_single : slot;
+            if (NP != 1 && !((L.payoff_mask >> p) & 1u)) continue;
+            double Ye = 0.0, Ya = 0.0, Y;
+            int64_t Yint = 0;
+            if (HAS_EXACT) {
+                const ExactT pf = ex.payoff(p, true, lev, ek, eb);
+                const ExactT pc = lev ? ex.payoff(p, false, lev - 1, ek, eb) : ExactT(0);
+                Ye = static_cast<double>(pf - pc);
+            }
+            if (HAS_TABLE) {
+                if (FIXED) {
+                    const int64_t pf = ax.payoff(p, true, lev, L);
+                    const int64_t pc = lev ? ax.payoff(p, false, lev - 1, L) : 0;
+                    Yint = pf - pc;
+                    Ya = ldexp(static_cast<double>(Yint), -L.fX);
+                } else {
+                    const float pf = ap.payoff(p, true, lev, L.fk, L.fb);
+                    const float pc = lev ? ap.payoff(p, false, lev - 1, L.fk, L.fb) : 0.0f;
+                    const float y = pf - pc;
+                    Ya = static_cast<double>(y);
+                }
+            }
+            if (EST == MLMC_EST_PLAIN) Y = Ye;
+            else if (EST == MLMC_EST_APPROX) Y = Ya;
+            else Y = Ye - Ya;
+            if (!__builtin_isfinite(Y)) { acc.nonfinite += 1; Y = 0.0; }
+            acc.s1[slot] += Y;
+            acc.s2[slot] = fma(Y, Y, acc.s2[slot]);
+            if (EST == MLMC_EST_CORR) {
+                acc.e1[slot] += Ye;
+                acc.e2[slot] = fma(Ye, Ye, acc.e2[slot]);
+            }
+            if (FIXED && EST == MLMC_EST_APPROX) {
+                acc.i1[slot] += Yint;
+                const uint64_t a = static_cast<uint64_t>(Yint < 0 ? -Yint : Yint);
+                const uint64_t sq = a * a;                       // |Y| < 2^32 by validation
+                const uint64_t lo = acc.i2lo[slot] + sq;
+                acc.i2hi[slot] += (lo < sq) ? 1u : 0u;
+                acc.i2lo[slot] = lo;
+            }
+            if (rec) {
+                rec->Y[p] = Y;
+                if (FIXED) {
+                    rec->Yraw[p] = Yint;
+                } else {
+                    union { double d; int64_t i; } u;
+                    u.d = Ya;
+                    rec->Yraw[p] = u.i;
+                }
+            }
+        }
+        acc.n += 1;
+        if (FIXED) acc.sat += ax.nsat;
+        if (rec) {
+            rec->XN_exact = HAS_EXACT ? static_cast<double>(ex.xf) : 0.0;
+            rec->XcN_exact = HAS_EXACT ? static_cast<double>(ex.xc) : 0.0;
+            if (FIXED) {
+                rec->XN_raw = ax.xf;
+                rec->XcN_raw = ax.xc;
+                rec->XN_approx = ldexp(static_cast<double>(ax.xf), -L.fX);
+                rec->XcN_approx = ldexp(static_cast<double>(ax.xc), -L.fX);
+            } else {
+                rec->XN_raw = rec->XcN_raw = 0;
+                rec->XN_approx = HAS_TABLE ? static_cast<double>(ap.xf) : 0.0;
+                rec->XcN_approx = HAS_TABLE ? static_cast<double>(ap.xc) : 0.0;
+            }
+            rec->first_word = first_word;
+            rec->first_index = first_index;
+            rec->saturations = FIXED ? ax.nsat : 0u;
+            rec->reserved = 0u;
+        }
+    }
+};
+
+}  // namespace mlmc

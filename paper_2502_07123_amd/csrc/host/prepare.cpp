@@ -1,0 +1,350 @@
+// Host preparation of a level launch: validation, constants, Method-1 table
+// (Section 3.1), step tables and kernel-variant choice.
+#include "prepare.hpp"
+
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "../device/fixed.hpp"
+#include "../device/norminv.hpp"
+#include "../device/paths.hpp"
+
+namespace mlmc {
+
+int popcount32(uint32_t v) {
+    int c = 0;
+    for (; v; v &= v - 1) ++c;
+    return c;
+}
+
+static int ctz32(uint32_t v) {
+    int c = 0;
+    while (v && !(v & 1u)) { v >>= 1; ++c; }
+    return c;
+}
+
+// ------------------------------------------------------------ Method-1 table
+// Phi^-1(k 2^-q) in long double: a bisection-safe start from the FP64 rational
+// approximation of the library, then Newton steps on Phi(x) - p with
+// Phi(x) = erfc(-x / sqrt 2) / 2 (relative accuracy ~1e-19 in the tails).
+static long double Phi_ld(long double x) { return 0.5L * erfcl(-x / sqrtl(2.0L)); }
+
+static long double phi_ld(long double x) {
+    return expl(-0.5L * x * x) / sqrtl(2.0L * 3.141592653589793238462643383279502884L);
+}
+
+static long double quantile_ld(uint64_t k, int q) {
+    const uint64_t n = uint64_t(1) << q;
+    if (2 * k == n) return 0.0L;
+    const bool upper = 2 * k > n;
+    const uint64_t kk = upper ? n - k : k;            // p = kk 2^-q <= 1/2, exact
+    const long double p = ldexpl(static_cast<long double>(kk), -q);
+    // start: the library's FP64 inverse normal at the nearest 32-bit grid point
+    const uint64_t J = static_cast<uint64_t>(ldexpl(p, 32));
+    long double x = norminv_f64(static_cast<uint32_t>(J > 0 ? J - 1 : 0));
+    for (int it = 0; it < 4; ++it) x -= (Phi_ld(x) - p) / phi_ld(x);
+    return upper ? -x : x;
+}
+
+const std::vector<long double>& method1_table(int q) {
+    static std::mutex mtx;
+    static std::map<int, std::vector<long double>> cache;
+    std::lock_guard<std::mutex> lock(mtx);
+    auto it = cache.find(q);
+    if (it != cache.end()) return it->second;
+    const uint64_t n = uint64_t(1) << q;
+    std::vector<long double> a(n + 1);
+    for (uint64_t k = 1; k < n; ++k) a[k] = quantile_ld(k, q);
+    std::vector<long double> T(n);
+    const long double scale = static_cast<long double>(n);
+    // T[k] = 2^q (phi(a_k) - phi(a_{k+1})); for interior k written as
+    // -phi(a_k) expm1(-(a_{k+1} - a_k)(a_{k+1} + a_k) / 2) to avoid cancellation.
+    for (uint64_t k = 0; k < n / 2; ++k) {
+        long double v;
+        if (k == 0) {
+            v = -phi_ld(a[1]);
+        } else {
+            const long double lo = a[k], hi = a[k + 1];
+            v = -phi_ld(lo) * expm1l(-0.5L * (hi - lo) * (hi + lo));
+        }
+        T[k] = scale * v;
+        T[n - 1 - k] = -T[k];                           // antisymmetry
+    }
+    return cache.emplace(q, std::move(T)).first->second;
+}
+
+static uint16_t to_half_bits(long double x) {
+    // round-to-nearest-even to IEEE binary16 (normal and subnormal; no overflow here)
+    const uint16_t sign = std::signbit(x) ? 0x8000u : 0u;
+    x = fabsl(x);
+    if (x == 0.0L) return sign;
+    int e;
+    frexpl(x, &e);                                     // x = m 2^e, m in [0.5, 1)
+    int exp16 = e - 1;                                 // x = 1.f 2^exp16
+    if (exp16 < -14) exp16 = -14;                      // subnormal spacing 2^-24
+    const long double m = nearbyintl(ldexpl(x, 10 - exp16));   // 11-bit significand
+    long double mm = m;
+    int ee = exp16;
+    if (mm >= 2048.0L) { mm /= 2.0L; ++ee; }
+    const uint32_t mant = static_cast<uint32_t>(mm);
+    if (mant < 1024u) return static_cast<uint16_t>(sign | mant);   // subnormal
+    return static_cast<uint16_t>(sign | ((ee + 15) << 10) | (mant - 1024u));
+}
+
+static bool quantize_ld(long double x, int f, int w, int64_t& out) {
+    const long double y = floorl(ldexpl(x, f) + 0.5L);          // R7: ties toward +inf
+    const long double hi = ldexpl(1.0L, w - 1) - 1.0L, lo = -ldexpl(1.0L, w - 1);
+    if (y > hi || y < lo) return false;
+    out = static_cast<int64_t>(y);
+    return true;
+}
+
+// quantise an FP64 value exactly (saturating silently: constants are inputs)
+static int64_t quantize_double(double x, int f, int w) {
+    const long double y = floorl(ldexpl(static_cast<long double>(x), f) + 0.5L);
+    const long double hi = ldexpl(1.0L, w - 1) - 1.0L, lo = -ldexpl(1.0L, w - 1);
+    return static_cast<int64_t>(y > hi ? hi : (y < lo ? lo : y));
+}
+
+mlmc_status build_table_bytes(int q, int arith, int frac_bits, void* out, std::string& err) {
+    if (q < 1 || q > 16) { err = "table_bits must be 1..16"; return MLMC_E_INVALID; }
+    if (!out) { err = "out is NULL"; return MLMC_E_INVALID; }
+    const auto& T = method1_table(q);
+    const size_t n = T.size();
+    switch (arith) {
+        case MLMC_ARITH_FP64: {
+            double* o = static_cast<double*>(out);
+            for (size_t k = 0; k < n; ++k) o[k] = static_cast<double>(T[k]);
+            return MLMC_OK;
+        }
+        case MLMC_ARITH_FP32: {
+            float* o = static_cast<float*>(out);
+            for (size_t k = 0; k < n; ++k) o[k] = static_cast<float>(T[k]);
+            return MLMC_OK;
+        }
+        case MLMC_ARITH_FP16: {
+            uint16_t* o = static_cast<uint16_t*>(out);
+            for (size_t k = 0; k < n; ++k) o[k] = to_half_bits(T[k]);
+            return MLMC_OK;
+        }
+        case MLMC_ARITH_FIXED: {
+            if (frac_bits < 0 || frac_bits > 28) { err = "frac_bits must be 0..28"; return MLMC_E_INVALID; }
+            int32_t* o = static_cast<int32_t*>(out);
+            for (size_t k = 0; k < n; ++k) {
+                int64_t v;
+                if (!quantize_ld(T[k], frac_bits, 32, v)) { err = "table value exceeds 32 bits"; return MLMC_E_INVALID; }
+                o[k] = static_cast<int32_t>(v);
+            }
+            return MLMC_OK;
+        }
+        default:
+            err = "unknown arith";
+            return MLMC_E_INVALID;
+    }
+}
+
+// ---------------------------------------------------------------- validation
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+mlmc_status validate_problem(const mlmc_problem* p, std::string& err) {
+    if (!p) { err = "problem is NULL"; return MLMC_E_INVALID; }
+    if (p->struct_size != sizeof(mlmc_problem)) { err = "mlmc_problem.struct_size mismatch"; return MLMC_E_VERSION; }
+    if (p->scheme != MLMC_EULER && p->scheme != MLMC_MILSTEIN) { err = "scheme must be EULER or MILSTEIN"; return MLMC_E_INVALID; }
+    if (p->payoff_mask == 0 || p->payoff_mask >= (1u << MLMC_NPAYOFF)) { err = "payoff_mask must be a non-empty set of MLMC_PAY_* bits"; return MLMC_E_INVALID; }
+    if (!finite_pos(p->S0) || !finite_pos(p->K) || !finite_pos(p->sigma) || !finite_pos(p->T)) { err = "S0, K, sigma and T must be finite and > 0"; return MLMC_E_INVALID; }
+    if (!std::isfinite(p->r) || p->r < 0.0) { err = "r must be finite and >= 0"; return MLMC_E_INVALID; }
+    if ((p->payoff_mask >> MLMC_PAY_BARRIER) & 1u) {
+        if (!std::isfinite(p->barrier) || p->barrier < 0.0 || p->barrier >= p->S0) { err = "barrier must satisfy 0 <= barrier < S0"; return MLMC_E_INVALID; }
+    }
+    return MLMC_OK;
+}
+
+static bool fixed_vars_used(int v, bool mil) {
+    switch (v) {
+        case MLMC_V_CON3: case MLMC_V_ZSQ: case MLMC_V_ZM1: case MLMC_V_MUL3: case MLMC_V_SUM2:
+            return mil;
+        default:
+            return true;
+    }
+}
+
+mlmc_status validate_precision(const mlmc_precision* prec, int estimator, const mlmc_problem* p,
+                               std::string& err) {
+    if (!prec) { err = "precision is NULL"; return MLMC_E_INVALID; }
+    if (prec->struct_size != sizeof(mlmc_precision)) { err = "mlmc_precision.struct_size mismatch"; return MLMC_E_VERSION; }
+    if (estimator == MLMC_EST_PLAIN) {
+        if (prec->arith != MLMC_ARITH_FP64 && prec->arith != MLMC_ARITH_FP32) { err = "PLAIN supports FP64 and FP32"; return MLMC_E_INVALID; }
+        if (prec->packed) { err = "packed indices apply to APPROX only"; return MLMC_E_INVALID; }
+        return MLMC_OK;
+    }
+    if (prec->arith != MLMC_ARITH_FP32 && prec->arith != MLMC_ARITH_FIXED) { err = "APPROX/CORR support FP32 and FIXED arithmetic"; return MLMC_E_INVALID; }
+    if (prec->table_bits < 1 || prec->table_bits > 12) { err = "table_bits must be 1..12"; return MLMC_E_INVALID; }
+    if (prec->packed) {
+        if (estimator != MLMC_EST_APPROX) { err = "packed indices apply to APPROX only"; return MLMC_E_INVALID; }
+        if (prec->arith != MLMC_ARITH_FP32) { err = "packed indices need FP32 arithmetic"; return MLMC_E_INVALID; }
+        const int F = 32 / prec->table_bits;
+        if (F != 4 && F != 5 && F != 8) { err = "packed indices need table_bits in {4, 6, 7, 8}"; return MLMC_E_INVALID; }
+    }
+    if (prec->arith != MLMC_ARITH_FIXED) return MLMC_OK;
+    const bool mil = p->scheme == MLMC_MILSTEIN;
+    const int* w = prec->word_bits;
+    const int* f = prec->frac_bits;
+    for (int v = 0; v < MLMC_NVARS; ++v) {
+        if (!fixed_vars_used(v, mil)) continue;
+        const int wmax = v == MLMC_V_Z ? 31 : 32;
+        if (w[v] < 2 || w[v] > wmax) { err = "word_bits out of range (2..32, Z 2..31) for variable " + std::to_string(v); return MLMC_E_INVALID; }
+        if (f[v] < 0 || f[v] > 62) { err = "frac_bits out of range (0..62) for variable " + std::to_string(v); return MLMC_E_INVALID; }
+    }
+    auto mul_ok = [&](int a, int b, int d) { return f[a] + f[b] - f[d] >= 0 && f[a] + f[b] - f[d] <= 62; };
+    auto add_ok = [&](int a, int b, int d) {
+        const int fm = std::max(f[a], f[b]);
+        return std::abs(f[a] - f[b]) <= 30 && fm - f[d] >= 0 && fm - f[d] <= 62;
+    };
+    const int S = mil ? MLMC_V_SUM2 : MLMC_V_SUM1;
+    bool ok = mul_ok(MLMC_V_X, S, MLMC_V_MUL2) && add_ok(MLMC_V_X, MLMC_V_MUL2, MLMC_V_X) &&
+              mul_ok(MLMC_V_CON2, MLMC_V_Z, MLMC_V_MUL1) && add_ok(MLMC_V_CON1, MLMC_V_MUL1, MLMC_V_SUM1);
+    if (mil) {
+        ok = ok && mul_ok(MLMC_V_Z, MLMC_V_Z, MLMC_V_ZSQ) && f[MLMC_V_ZSQ] <= 30 &&
+             add_ok(MLMC_V_ZSQ, MLMC_V_ZSQ, MLMC_V_ZM1) && mul_ok(MLMC_V_CON3, MLMC_V_ZM1, MLMC_V_MUL3) &&
+             add_ok(MLMC_V_SUM1, MLMC_V_MUL3, MLMC_V_SUM2);
+    }
+    if (!ok) {
+        err = "fixed-point formats: every product needs f_dst <= f_a + f_b, every sum f_dst <= max(f_a, f_b) "
+              "and |f_a - f_b| <= 30 (zsq: f <= 30)";
+        return MLMC_E_INVALID;
+    }
+    return MLMC_OK;
+}
+
+mlmc_status validate_all(const mlmc_problem* p, int32_t level, uint64_t n_paths, uint64_t path_offset,
+                         const mlmc_precision* prec, int32_t estimator, std::string& err) {
+    mlmc_status s = validate_problem(p, err);
+    if (s != MLMC_OK) return s;
+    if (level < 0 || level > 20) { err = "level must be 0..20"; return MLMC_E_INVALID; }
+    if (estimator < MLMC_EST_PLAIN || estimator > MLMC_EST_CORR) { err = "estimator must be PLAIN, APPROX or CORR"; return MLMC_E_INVALID; }
+    if (n_paths < 1) { err = "n_paths must be >= 1"; return MLMC_E_INVALID; }
+    if (path_offset > (uint64_t(1) << 40) || n_paths > (uint64_t(1) << 40) - path_offset) { err = "path_offset + n_paths must be <= 2^40"; return MLMC_E_INVALID; }
+    return validate_precision(prec, estimator, p, err);
+}
+
+// --------------------------------------------------------------- level prep
+static FxOp mul_op(const int* f, const int* w, int a, int b, int d) {
+    return FxOp{0, 0, f[a] + f[b] - f[d], w[d]};
+}
+static FxOp mul_op_fz(const int* f, const int* w, int fa, int fb, int d) {
+    return FxOp{0, 0, fa + fb - f[d], w[d]};
+}
+static FxOp add_op(const int* f, const int* w, int fa, int fb, int d) {
+    const int fm = std::max(fa, fb);
+    return FxOp{fm - fa, fm - fb, fm - f[d], w[d]};
+}
+
+mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_precision* prec,
+                          int32_t estimator, LevelPrep& out, std::string& err) {
+    LevelDev& L = out.dev;
+    std::memset(&L, 0, sizeof(L));
+    const bool mil = p->scheme == MLMC_MILSTEIN;
+    // constants in the order the method's reference computes them (FP64)
+    const double h = p->T / static_cast<double>(uint64_t(1) << level);
+    L.con1 = p->r * h;
+    L.con1c = p->r * (2.0 * h);
+    L.con2 = p->sigma * std::sqrt(h);
+    L.con3 = ((0.5 * p->sigma) * p->sigma) * h;
+    L.k = p->K / p->S0;
+    L.b = p->barrier / p->S0;
+    L.fcon1 = static_cast<float>(L.con1);
+    L.fcon1c = static_cast<float>(L.con1c);
+    L.fcon2 = static_cast<float>(L.con2);
+    L.fcon3 = static_cast<float>(L.con3);
+    L.f2con3 = static_cast<float>(2.0 * L.con3);
+    L.fk = static_cast<float>(L.k);
+    L.fb = static_cast<float>(L.b);
+    L.level = level;
+    L.scheme = p->scheme;
+    L.payoff_mask = p->payoff_mask;
+    L.payoff_single = ctz32(p->payoff_mask);
+    L.q = prec->table_bits;
+
+    Variant& v = out.variant;
+    v.est = estimator;
+    v.arith = prec->arith;
+    v.scheme = p->scheme;
+    v.np = popcount32(p->payoff_mask) == 1 ? 1 : NPAY;
+    v.track = ((p->payoff_mask >> MLMC_PAY_ASIAN) & 1u) || ((p->payoff_mask >> MLMC_PAY_BARRIER) & 1u);
+    v.fields = (estimator == MLMC_EST_APPROX && prec->packed) ? 32 / prec->table_bits : 1;
+    out.table.clear();
+    if (estimator == MLMC_EST_PLAIN) return MLMC_OK;
+
+    const int q = prec->table_bits;
+    const uint32_t n = 1u << q;
+    const auto& T = method1_table(q);
+    L.table_entries = n;
+    if (prec->arith == MLMC_ARITH_FP32) {
+        // (Z~_k, s_k): s_k is the fine step's multiplier of Z~_k, formed with the
+        // same FP32 operations the kernels use on the coarse path
+        out.table.resize(static_cast<size_t>(n) * 8);
+        for (uint32_t k = 0; k < n; ++k) {
+            const float z = static_cast<float>(T[k]);
+            const float sf = mil ? multiplier32<true>(z, L.fcon1, L.fcon2, L.fcon3, 1.0f)
+                                 : multiplier32<false>(z, L.fcon1, L.fcon2, L.fcon3, 1.0f);
+            std::memcpy(&out.table[8 * k], &z, 4);
+            std::memcpy(&out.table[8 * k + 4], &sf, 4);
+        }
+    } else {
+        const int* f = prec->frac_bits;
+        const int* w = prec->word_bits;
+        L.fX = f[MLMC_V_X];
+        L.wX = w[MLMC_V_X];
+        L.icon1 = quantize_double(L.con1, f[MLMC_V_CON1], w[MLMC_V_CON1]);
+        L.icon1c = quantize_double(L.con1c, f[MLMC_V_CON1], w[MLMC_V_CON1]);
+        L.icon2 = quantize_double(L.con2, f[MLMC_V_CON2], w[MLMC_V_CON2]);
+        L.icon3 = mil ? quantize_double(L.con3, f[MLMC_V_CON3], w[MLMC_V_CON3]) : 0;
+        L.ik = quantize_double(L.k, f[MLMC_V_X], w[MLMC_V_X]);
+        L.ib = quantize_double(L.b, f[MLMC_V_X], w[MLMC_V_X]);
+        const int S = mil ? MLMC_V_SUM2 : MLMC_V_SUM1;
+        L.op_mul2 = mul_op(f, w, MLMC_V_X, S, MLMC_V_MUL2);
+        L.op_addX = add_op(f, w, f[MLMC_V_X], f[MLMC_V_MUL2], MLMC_V_X);
+        L.op_mul1 = mul_op(f, w, MLMC_V_CON2, MLMC_V_Z, MLMC_V_MUL1);
+        L.op_sum1 = add_op(f, w, f[MLMC_V_CON1], f[MLMC_V_MUL1], MLMC_V_SUM1);
+        if (mil) {
+            L.op_zsq = mul_op_fz(f, w, f[MLMC_V_Z], f[MLMC_V_Z], MLMC_V_ZSQ);
+            L.op_zm1 = add_op(f, w, f[MLMC_V_ZSQ], f[MLMC_V_ZSQ], MLMC_V_ZM1);
+            L.op_mul3 = mul_op(f, w, MLMC_V_CON3, MLMC_V_ZM1, MLMC_V_MUL3);
+            L.op_sum2 = add_op(f, w, f[MLMC_V_SUM1], f[MLMC_V_MUL3], MLMC_V_SUM2);
+            L.izm_c2 = int64_t(2) << f[MLMC_V_ZSQ];
+        }
+        out.table.resize(static_cast<size_t>(n) * 8);
+        uint32_t nsat = 0;
+        for (uint32_t k = 0; k < n; ++k) {
+            int64_t z;
+            if (!quantize_ld(T[k], f[MLMC_V_Z], w[MLMC_V_Z], z)) {
+                err = "a table value does not fit Z's format";
+                return MLMC_E_OVERFLOW;
+            }
+            // the fine step's multiplier, Algorithm 1's chain on Z~_k (with con1)
+            const int64_t m1 = fx_mul(L.icon2, z, L.op_mul1, nsat);
+            int64_t s = fx_add(L.icon1, m1, L.op_sum1, nsat);
+            if (mil) {
+                const int64_t zq = fx_mul(z, z, L.op_zsq, nsat);
+                const int64_t zm = fx_add(zq, -(int64_t(1) << f[MLMC_V_ZSQ]), L.op_zm1, nsat);
+                const int64_t m3 = fx_mul(L.icon3, zm, L.op_mul3, nsat);
+                s = fx_add(s, m3, L.op_sum2, nsat);
+            }
+            const int32_t zi = static_cast<int32_t>(z), si = static_cast<int32_t>(s);
+            std::memcpy(&out.table[8 * k], &zi, 4);
+            std::memcpy(&out.table[8 * k + 4], &si, 4);
+        }
+        if (nsat) {
+            err = "the fixed-point formats saturate in the table-driven part of the step (mul1/sum1/zsq/zm1/mul3/sum2 of some table value)";
+            return MLMC_E_OVERFLOW;
+        }
+    }
+    L.table_bytes = static_cast<uint32_t>((out.table.size() + 15) & ~size_t(15));
+    out.table.resize(L.table_bytes, 0);
+    return MLMC_OK;
+}
+
+}  // namespace mlmc

@@ -1,0 +1,77 @@
+// The kernels' per-path code compiled for the host: a checker of the kernel
+// arithmetic (records and sums) that runs without a GPU.  Groups are processed in
+// order by one "thread", so per-path records equal the kernel's and sums differ
+// from the kernel's only by FP64 summation order.
+#include <cstring>
+#include <string>
+
+#include "device/paths.hpp"
+#include "host/prepare.hpp"
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+namespace mlmc {
+namespace {
+struct HostGroups {
+    const LevelDev* L;
+    const WorkDev* W;
+    const void* tab;
+    SlotDev out{};
+    template <class Tag>
+    void operator()(Tag) {
+        using B = PathBody<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields>;
+        const uint64_t N = uint64_t(1) << L->level;
+        const uint64_t S = group_span(L->level, B::WPB);
+        const uint64_t G = S >> L->level;
+        const uint64_t g0 = W->path_begin / G, g1 = (W->path_end - 1) / G + 1;
+        Acc<Tag::np> acc;
+        acc_zero(acc);
+        for (uint64_t g = g0; g < g1; ++g) B::run_group(*L, *W, g, tab, acc);
+        std::memset(&out, 0, sizeof(out));
+        for (int p = 0; p < Tag::np; ++p) {
+            out.s1[p] = acc.s1[p];
+            out.s2[p] = acc.s2[p];
+            out.e1[p] = acc.e1[p];
+            out.e2[p] = acc.e2[p];
+            out.i1[p] = acc.i1[p];
+            out.i2lo[p] = acc.i2lo[p];
+            out.i2hi[p] = acc.i2hi[p];
+        }
+        out.n = acc.n;
+        out.sat = acc.sat;
+        out.nonfinite = acc.nonfinite;
+    }
+};
+}  // namespace
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" mlmc_status mlmc_check_paths_host(const mlmc_problem* prob, int32_t level, uint64_t n_paths,
+                                             uint64_t path_offset, const mlmc_precision* prec,
+                                             int32_t estimator, uint64_t seed, uint32_t option_id,
+                                             mlmc_sums* out, mlmc_path_record* records) {
+    std::string err;
+    mlmc_status s = validate_all(prob, level, n_paths, path_offset, prec, estimator, err);
+    if (s != MLMC_OK) return s;
+    if (!out || n_paths > 65536) return MLMC_E_INVALID;
+    LevelPrep lp;
+    s = prepare_level(prob, level, prec, estimator, lp, err);
+    if (s != MLMC_OK) return s;
+    WorkDev W;
+    std::memset(&W, 0, sizeof(W));
+    W.c2 = stream_c2(level, estimator);
+    W.c3 = option_id;
+    W.k0 = static_cast<uint32_t>(seed);
+    W.k1 = static_cast<uint32_t>(seed >> 32);
+    W.path_begin = path_offset;
+    W.path_end = path_offset + n_paths;
+    W.debug = reinterpret_cast<uint64_t>(records);
+    HostGroups h{&lp.dev, &W, lp.table.empty() ? nullptr : lp.table.data()};
+    if (!dispatch_variant(lp.variant, h)) return MLMC_E_INVALID;
+    const bool single = popcount32(prob->payoff_mask) == 1;
+    int i = 0;
+    for (int p = 0; p < MLMC_NPAYOFF; ++p)
+        if ((prob->payoff_mask >> p) & 1u) slot_to_sums(h.out, single ? 0 : p, out[i++]);
+    return MLMC_OK;
+}

@@ -1,0 +1,90 @@
+// Kernel variants and launch entry points (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace mlmc {
+
+// One compiled instance of the path body: estimator, arithmetic of the table
+// (or plain) side, scheme, payoffs per launch (1 or NPAY), whether Asian sums and
+// running minima are kept, and indices per 32-bit word (1 = unpacked).
+struct Variant {
+    int est, arith, scheme, np;
+    bool track;
+    int fields;
+};
+
+template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
+struct VTag {
+    static constexpr int est = EST, arith = ARITH, np = NP, fields = F;
+    static constexpr bool mil = MIL, track = TRACK;
+};
+
+namespace detail {
+template <int EST, int ARITH, bool MIL, int F, class Fn>
+bool pick_np(const Variant& v, Fn& fn) {
+    if (v.np != 1) { fn(VTag<EST, ARITH, MIL, NPAY, true, F>{}); return true; }
+    if (v.track) { fn(VTag<EST, ARITH, MIL, 1, true, F>{}); return true; }
+    fn(VTag<EST, ARITH, MIL, 1, false, F>{});
+    return true;
+}
+template <int EST, int ARITH, int F, class Fn>
+bool pick_mil(const Variant& v, Fn& fn) {
+    return v.scheme == MLMC_MILSTEIN ? pick_np<EST, ARITH, true, F>(v, fn)
+                                     : pick_np<EST, ARITH, false, F>(v, fn);
+}
+}  // namespace detail
+
+// Calls fn(VTag<...>{}) for the compiled instance matching v; false if none.
+template <class Fn>
+bool dispatch_variant(const Variant& v, Fn& fn) {
+    using namespace detail;
+    switch (v.est) {
+        case MLMC_EST_PLAIN:
+            if (v.fields != 1) return false;
+            if (v.arith == MLMC_ARITH_FP64) return pick_mil<MLMC_EST_PLAIN, MLMC_ARITH_FP64, 1>(v, fn);
+            if (v.arith == MLMC_ARITH_FP32) return pick_mil<MLMC_EST_PLAIN, MLMC_ARITH_FP32, 1>(v, fn);
+            return false;
+        case MLMC_EST_APPROX:
+            if (v.arith == MLMC_ARITH_FIXED)
+                return v.fields == 1 && pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FIXED, 1>(v, fn);
+            if (v.arith != MLMC_ARITH_FP32) return false;
+            switch (v.fields) {
+                case 1: return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP32, 1>(v, fn);
+                case 4: return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP32, 4>(v, fn);
+                case 5: return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP32, 5>(v, fn);
+                case 8: return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP32, 8>(v, fn);
+                default: return false;
+            }
+        case MLMC_EST_CORR:
+            if (v.fields != 1) return false;
+            if (v.arith == MLMC_ARITH_FIXED) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FIXED, 1>(v, fn);
+            if (v.arith == MLMC_ARITH_FP32) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP32, 1>(v, fn);
+            return false;
+        default:
+            return false;
+    }
+}
+
+struct VariantInfo {
+    void* fn;              // kernel
+    int wpb;               // normals per Philox block
+    int tab_bytes;         // bytes per table entry (0: no table)
+    int max_block;         // largest block size the kernel was compiled for
+};
+
+VariantInfo variant_info(const Variant& v);   // fn == nullptr when not compiled
+
+hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,
+                        hipStream_t st, const TileDev* tiles, uint32_t n_tiles,
+                        const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
+                        SlotDev* slots);
+
+// sums[rd.sums] (+)= ordered sum of the work's tile slots; compact[w] = the result
+hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
+                         SlotDev* sums, SlotDev* compact);
+
+}  // namespace mlmc

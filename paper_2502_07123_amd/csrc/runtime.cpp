@@ -1,0 +1,702 @@
+// C-ABI entry points and the runtime behind them: context and workspace, launch
+// planning (works -> tiles -> slots), execution on the caller's stream, the
+// adaptive nested MLMC driver (Sections 2.1, 2.2 and 6), batched pricing and the
+// continuous-batching server.
+#include "runtime.hpp"
+
+#include "device/philox.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <tuple>
+
+namespace mlmc {
+
+double now_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+mlmc_status fail(mlmc_context* ctx, mlmc_status s, const std::string& msg) {
+    if (ctx) {
+        ctx->err = msg;
+        if (s == MLMC_E_DEVICE) ctx->poisoned = true;
+    }
+    return s;
+}
+
+#define HIPCHK(call)                                                                   \
+    do {                                                                               \
+        const hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess)                                                          \
+            return fail(ctx, MLMC_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static std::string prep_key(const mlmc_problem* p, int level, const mlmc_precision* prec, int est) {
+    std::string k;
+    k.append(reinterpret_cast<const char*>(p), sizeof(*p));
+    k.append(reinterpret_cast<const char*>(&level), sizeof(level));
+    k.append(reinterpret_cast<const char*>(prec), sizeof(*prec));
+    k.append(reinterpret_cast<const char*>(&est), sizeof(est));
+    return k;
+}
+
+void slot_to_sums(const SlotDev& s, int i, mlmc_sums& o) {
+    o.n = s.n;
+    o.sum1 = s.s1[i];
+    o.sum2 = s.s2[i];
+    o.isum1 = s.i1[i];
+    o.isum2_lo = s.i2lo[i];
+    o.isum2_hi = s.i2hi[i];
+    o.esum1 = s.e1[i];
+    o.esum2 = s.e2[i];
+    o.saturations = s.sat;
+    o.nonfinite = s.nonfinite;
+}
+
+static mlmc_status ensure_pinned(mlmc_context* ctx, size_t bytes) {
+    if (ctx->pinned_bytes >= bytes) return MLMC_OK;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+    return MLMC_OK;
+}
+
+namespace {
+using VKey = std::tuple<int, int, int, int, bool, int>;
+VKey vkey(const Variant& v) { return VKey{v.est, v.arith, v.scheme, v.np, v.track, v.fields}; }
+
+struct LaunchGroup {
+    Variant v;
+    VariantInfo vi;
+    std::vector<uint32_t> works;
+    uint32_t t0 = 0, t1 = 0, block = 0, lds = 0;
+};
+}  // namespace
+
+mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uint32_t n_sums,
+                      std::vector<SlotDev>& out) {
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    out.clear();
+    if (works.empty()) return MLMC_OK;
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    HIPCHK(hipSetDevice(ctx->device));
+
+    // 1. levels, tables, works
+    std::vector<LevelDev> levels;
+    std::vector<Variant> lvl_var;
+    std::vector<uint8_t> tables;
+    std::map<std::string, uint32_t> lvl_index;
+    std::vector<WorkDev> wdev(works.size());
+    if (ctx->prep_cache.size() > 4096) ctx->prep_cache.clear();
+    for (size_t i = 0; i < works.size(); ++i) {
+        const WorkSpec& w = works[i];
+        const std::string key = prep_key(w.prob, w.level, w.prec, w.est);
+        auto it = lvl_index.find(key);
+        uint32_t li;
+        if (it == lvl_index.end()) {
+            auto pc = ctx->prep_cache.find(key);
+            if (pc == ctx->prep_cache.end()) {
+                LevelPrep lp;
+                std::string err;
+                const mlmc_status s = prepare_level(w.prob, w.level, w.prec, w.est, lp, err);
+                if (s != MLMC_OK) return fail(ctx, s, err);
+                pc = ctx->prep_cache.emplace(key, std::move(lp)).first;
+            }
+            LevelDev L = pc->second.dev;
+            if (!pc->second.table.empty()) {
+                L.table_off = static_cast<uint32_t>(tables.size());
+                tables.insert(tables.end(), pc->second.table.begin(), pc->second.table.end());
+            }
+            li = static_cast<uint32_t>(levels.size());
+            lvl_index.emplace(key, li);
+            levels.push_back(L);
+            lvl_var.push_back(pc->second.variant);
+        } else {
+            li = it->second;
+        }
+        WorkDev& d = wdev[i];
+        d.lvl = li;
+        d.c2 = stream_c2(w.level, w.est);
+        d.c3 = w.option;
+        d.k0 = static_cast<uint32_t>(w.seed);
+        d.k1 = static_cast<uint32_t>(w.seed >> 32);
+        d.sums = w.sums;
+        d.path_begin = w.path_begin;
+        d.path_end = w.path_begin + w.n;
+        d.debug = w.debug;
+    }
+
+    // 2. variants -> tiles (a work's tiles are contiguous; slot = tile index)
+    std::map<VKey, LaunchGroup> groups;
+    for (size_t i = 0; i < works.size(); ++i) {
+        const Variant& v = lvl_var[wdev[i].lvl];
+        auto& g = groups[vkey(v)];
+        g.v = v;
+        g.works.push_back(static_cast<uint32_t>(i));
+    }
+    std::vector<TileDev> tiles;
+    std::vector<ReduceDev> reds(works.size());
+    for (auto& kv : groups) {
+        LaunchGroup& g = kv.second;
+        g.vi = variant_info(g.v);
+        if (!g.vi.fn) return fail(ctx, MLMC_E_INVALID, "no compiled kernel for this estimator/arithmetic/packing");
+        g.block = std::min<uint32_t>(g.vi.tab_bytes && g.v.est == MLMC_EST_APPROX ? ctx->tune.block_table
+                                                                                  : ctx->tune.block_exact,
+                                     static_cast<uint32_t>(g.vi.max_block));
+        g.t0 = static_cast<uint32_t>(tiles.size());
+        for (uint32_t wi : g.works) {
+            const WorkSpec& w = works[wi];
+            const uint64_t N = uint64_t(1) << w.level;
+            const uint64_t S = group_span(w.level, static_cast<uint32_t>(g.vi.wpb));
+            const uint64_t G = S >> w.level;                       // paths per group
+            const uint64_t g0 = w.path_begin / G;
+            const uint64_t g1 = (w.path_begin + w.n - 1) / G + 1;
+            uint64_t per = uint64_t(g.block) * std::max<uint64_t>(1, ctx->tune.tile_steps / (g.block * S));
+            const uint64_t max_tiles = 1u << 16;
+            if ((g1 - g0 + per - 1) / per > max_tiles) per = (g1 - g0 + max_tiles - 1) / max_tiles;
+            reds[wi].slot_begin = static_cast<uint32_t>(tiles.size());
+            for (uint64_t gg = g0; gg < g1; gg += per) {
+                TileDev t;
+                t.work = wi;
+                t.slot = static_cast<uint32_t>(tiles.size());
+                t.group_begin = gg;
+                t.n_groups = static_cast<uint32_t>(std::min(per, g1 - gg));
+                t.pad = 0;
+                tiles.push_back(t);
+            }
+            reds[wi].slot_end = static_cast<uint32_t>(tiles.size());
+            reds[wi].sums = w.sums;
+            reds[wi].accumulate = w.accumulate ? 1u : 0u;
+            g.lds = std::max<uint32_t>(g.lds, levels[wdev[wi].lvl].table_bytes);
+        }
+        g.t1 = static_cast<uint32_t>(tiles.size());
+    }
+    if (tiles.size() >= (size_t(1) << 31)) return fail(ctx, MLMC_E_NOMEM, "too many tiles");
+
+    // 3. workspace layout: [sums | compact | levels | works | tables | tiles | reds | slots]
+    const size_t o_sums = 0;
+    const size_t o_comp = align_up(o_sums + size_t(n_sums) * sizeof(SlotDev), 256);
+    const size_t o_lvl = align_up(o_comp + works.size() * sizeof(SlotDev), 256);
+    const size_t o_work = align_up(o_lvl + levels.size() * sizeof(LevelDev), 256);
+    const size_t o_tab = align_up(o_work + wdev.size() * sizeof(WorkDev), 256);
+    const size_t o_tile = align_up(o_tab + tables.size(), 256);
+    const size_t o_red = align_up(o_tile + tiles.size() * sizeof(TileDev), 256);
+    const size_t o_slot = align_up(o_red + reds.size() * sizeof(ReduceDev), 256);
+    const size_t total = o_slot + tiles.size() * sizeof(SlotDev);
+    if (total > ctx->ws_bytes)
+        return fail(ctx, MLMC_E_NOMEM, "workspace too small: need " + std::to_string(total) + " bytes");
+    const size_t up_bytes = o_slot - o_lvl;
+    const size_t down_bytes = works.size() * sizeof(SlotDev);
+    mlmc_status st = ensure_pinned(ctx, std::max(up_bytes, down_bytes));
+    if (st != MLMC_OK) return st;
+    // the pinned buffer may still be read by a previous copy: the stream is synchronised
+    // at the end of every run, so it is free here
+    uint8_t* h = ctx->pinned;
+    std::memset(h, 0, up_bytes);
+    std::memcpy(h + (o_lvl - o_lvl), levels.data(), levels.size() * sizeof(LevelDev));
+    std::memcpy(h + (o_work - o_lvl), wdev.data(), wdev.size() * sizeof(WorkDev));
+    if (!tables.empty()) std::memcpy(h + (o_tab - o_lvl), tables.data(), tables.size());
+    std::memcpy(h + (o_tile - o_lvl), tiles.data(), tiles.size() * sizeof(TileDev));
+    std::memcpy(h + (o_red - o_lvl), reds.data(), reds.size() * sizeof(ReduceDev));
+    uint8_t* d = ctx->ws;
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s));
+
+    // 4. path kernels, one per variant, then the fixed-order reduction
+    const uint32_t max_grid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * ctx->tune.blocks_per_cu;
+    if (ctx->timing && ctx->events.size() < 2 * groups.size()) {
+        while (ctx->events.size() < 2 * groups.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->events.push_back(e);
+        }
+    }
+    size_t gi = 0;
+    for (auto& kv : groups) {
+        LaunchGroup& g = kv.second;
+        const uint32_t nt = g.t1 - g.t0;
+        if (!nt) continue;
+        const uint32_t grid = std::min(nt, max_grid);
+        if (ctx->timing) HIPCHK(hipEventRecord(ctx->events[2 * gi], s));
+        HIPCHK(launch_paths(g.vi, grid, g.block, g.lds, s,
+                            reinterpret_cast<const TileDev*>(d + o_tile) + g.t0, nt,
+                            reinterpret_cast<const WorkDev*>(d + o_work),
+                            reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab,
+                            reinterpret_cast<SlotDev*>(d + o_slot)));
+        if (ctx->timing) HIPCHK(hipEventRecord(ctx->events[2 * gi + 1], s));
+        ++gi;
+    }
+    HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s,
+                         reinterpret_cast<const SlotDev*>(d + o_slot),
+                         reinterpret_cast<const ReduceDev*>(d + o_red),
+                         reinterpret_cast<SlotDev*>(d + o_sums), reinterpret_cast<SlotDev*>(d + o_comp)));
+    HIPCHK(hipMemcpyAsync(h, d + o_comp, down_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out.resize(works.size());
+    std::memcpy(out.data(), h, down_bytes);
+    if (ctx->timing) {
+        gi = 0;
+        for (auto& kv : groups) {
+            LaunchGroup& g = kv.second;
+            if (g.t1 == g.t0) continue;
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 * gi], ctx->events[2 * gi + 1]));
+            ++gi;
+            uint64_t steps = 0;
+            for (uint32_t wi : g.works) steps += works[wi].n << works[wi].level;
+            mlmc_kernel_stat* st = nullptr;
+            for (auto& x : ctx->stats)
+                if (x.estimator == g.v.est && x.arith == g.v.arith && x.scheme == g.v.scheme &&
+                    x.fields == g.v.fields && x.payoffs == g.v.np && x.track == int(g.v.track))
+                    st = &x;
+            if (!st) {
+                mlmc_kernel_stat z;
+                std::memset(&z, 0, sizeof(z));
+                z.estimator = g.v.est;
+                z.arith = g.v.arith;
+                z.scheme = g.v.scheme;
+                z.fields = g.v.fields;
+                z.payoffs = g.v.np;
+                z.track = g.v.track ? 1 : 0;
+                ctx->stats.push_back(z);
+                st = &ctx->stats.back();
+            }
+            st->launches += 1;
+            st->ms += ms;
+            st->path_steps += steps;
+        }
+    }
+    return MLMC_OK;
+}
+
+// ------------------------------------------------------------- adaptive MLMC
+static int n_est(const OptionRun& o) { return o.cfg.nested ? 2 : 1; }
+static int est_at(const OptionRun& o, int i) {
+    return o.cfg.nested ? (i == 0 ? MLMC_EST_APPROX : MLMC_EST_CORR) : MLMC_EST_PLAIN;
+}
+static double s_mean(const SlotDev& s) { return s.n ? s.s1[0] / static_cast<double>(s.n) : 0.0; }
+static double s_var(const SlotDev& s) {
+    if (s.n < 2) return 0.0;
+    const double n = static_cast<double>(s.n);
+    return std::max((s.s2[0] - s.s1[0] * s.s1[0] / n) / (n - 1.0), 0.0);       // R9
+}
+
+void option_init(OptionRun& o) {
+    o.L = o.cfg.L_min;
+    o.done = false;
+    o.sweeps = 0;
+    o.path_steps = 0;
+    o.saturations = 0;
+    o.sums.assign(static_cast<size_t>(o.cfg.L_max) + 1, std::array<SlotDev, 3>{});
+    for (auto& a : o.sums) for (auto& s : a) std::memset(&s, 0, sizeof(s));
+    o.t_start = now_seconds();
+}
+
+static double eps_internal(const OptionRun& o) {
+    const double scale = std::exp(-o.prob.r * o.prob.T) * (o.cfg.eps_units == 1 ? o.prob.S0 : 1.0);
+    return o.cfg.eps / scale;
+}
+
+static double est_cost(const OptionRun& o, int est) {
+    return est == MLMC_EST_PLAIN ? o.cfg.cost_plain
+                                 : (est == MLMC_EST_APPROX ? o.cfg.cost_approx : o.cfg.cost_corr);
+}
+
+static double weak_alpha(const std::vector<double>& m) {
+    // least-squares slope of log2 |mean_l| over l >= 1; floor 1/2; 1 if < 2 points
+    std::vector<double> x, y;
+    for (size_t l = 1; l < m.size(); ++l)
+        if (m[l] != 0.0) { x.push_back(double(l)); y.push_back(std::log2(std::fabs(m[l]))); }
+    if (x.size() < 2) return 1.0;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    const double n = double(x.size());
+    for (size_t i = 0; i < x.size(); ++i) { sx += x[i]; sy += y[i]; sxx += x[i] * x[i]; sxy += x[i] * y[i]; }
+    const double slope = (n * sxy - sx * sy) / (n * sxx - sx * sx);
+    return std::max(0.5, -slope);
+}
+
+std::vector<Pending> option_advance(OptionRun& o) {
+    std::vector<Pending> pend;
+    if (o.done) return pend;
+    const int ne = n_est(o);
+    for (int l = 0; l <= o.L; ++l)
+        for (int i = 0; i < ne; ++i) {
+            const uint64_t have = o.sums[l][est_at(o, i)].n;
+            if (have < o.cfg.n_pilot) pend.push_back({l, est_at(o, i), o.cfg.n_pilot - have});
+        }
+    if (!pend.empty()) return pend;
+    const double eps = eps_internal(o);
+    // optimal allocation over all (level, estimator) pairs with one multiplier
+    double lam = 0.0;
+    for (int l = 0; l <= o.L; ++l)
+        for (int i = 0; i < ne; ++i) {
+            const int e = est_at(o, i);
+            const double V = std::max(s_var(o.sums[l][e]), 1e-300);
+            lam += std::sqrt(V * est_cost(o, e) * std::ldexp(1.0, l));
+        }
+    lam /= o.cfg.theta * eps * eps;
+    for (int l = 0; l <= o.L; ++l)
+        for (int i = 0; i < ne; ++i) {
+            const int e = est_at(o, i);
+            const double V = std::max(s_var(o.sums[l][e]), 1e-300);
+            const double target = std::ceil(lam * std::sqrt(V / (est_cost(o, e) * std::ldexp(1.0, l))));
+            const uint64_t t = target > 1.8e19 ? UINT64_MAX : static_cast<uint64_t>(target);
+            if (t > o.sums[l][e].n) pend.push_back({l, e, t - o.sums[l][e].n});
+        }
+    if (!pend.empty()) return pend;
+    std::vector<double> means(o.L + 1, 0.0);
+    for (int l = 0; l <= o.L; ++l)
+        for (int i = 0; i < ne; ++i) means[l] += s_mean(o.sums[l][est_at(o, i)]);
+    const double alpha = weak_alpha(means);
+    const double bias = std::fabs(means[o.L]) / (std::pow(2.0, alpha) - 1.0);
+    if (bias > std::sqrt(1.0 - o.cfg.theta) * eps && o.L < o.cfg.L_max) {
+        o.L += 1;
+        for (int i = 0; i < ne; ++i) pend.push_back({o.L, est_at(o, i), o.cfg.n_pilot});
+        return pend;
+    }
+    o.done = true;
+    o.t_end = now_seconds();
+    return pend;
+}
+
+void option_result(const OptionRun& o, mlmc_result& r) {
+    std::memset(&r, 0, sizeof(r));
+    r.struct_size = sizeof(mlmc_result);
+    r.status = o.done ? MLMC_OK : MLMC_PENDING;
+    r.L = o.L;
+    r.sweeps = o.sweeps;
+    const double sc = std::exp(-o.prob.r * o.prob.T) * o.prob.S0;       // R4, R5a
+    double est = 0.0, var = 0.0;
+    for (int l = 0; l <= o.L; ++l)
+        for (int e = 0; e < 3; ++e) {
+            const SlotDev& s = o.sums[l][e];
+            r.level[l].n[e] = s.n;
+            r.level[l].mean[e] = s_mean(s);
+            r.level[l].var[e] = s_var(s);
+            if (s.n) {
+                est += s_mean(s);
+                var += s_var(s) / static_cast<double>(s.n);
+            }
+        }
+    r.estimate = sc * est;
+    r.variance = sc * sc * var;
+    r.seconds = o.t_end - o.t_start;
+    r.path_steps = o.path_steps;
+    r.saturations = o.saturations;
+}
+
+static mlmc_precision plain_precision(const OptionRun& o) {
+    mlmc_precision p;
+    std::memset(&p, 0, sizeof(p));
+    p.struct_size = sizeof(p);
+    p.arith = o.cfg.plain_arith;
+    p.table_bits = 8;
+    return p;
+}
+
+mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts, uint32_t n_sums) {
+    std::vector<mlmc_precision> plain(opts.size());
+    for (size_t i = 0; i < opts.size(); ++i) plain[i] = plain_precision(*opts[i]);
+    for (;;) {
+        std::vector<WorkSpec> works;
+        std::vector<std::pair<size_t, Pending>> who;
+        for (size_t i = 0; i < opts.size(); ++i) {
+            OptionRun& o = *opts[i];
+            if (o.done) continue;
+            for (const Pending& p : option_advance(o)) {
+                WorkSpec w;
+                w.prob = &o.prob;
+                w.level = p.level;
+                w.prec = p.est == MLMC_EST_PLAIN ? &plain[i] : &o.cfg.prec[p.level];
+                w.est = p.est;
+                w.seed = o.seed;
+                w.option = o.option;
+                w.path_begin = o.sums[p.level][p.est].n;
+                w.n = p.n;
+                w.sums = o.sums_base + static_cast<uint32_t>(p.level) * 3u + static_cast<uint32_t>(p.est);
+                w.debug = 0;
+                w.accumulate = o.sums[p.level][p.est].n > 0;
+                works.push_back(w);
+                who.emplace_back(i, p);
+            }
+        }
+        if (works.empty()) return MLMC_OK;
+        // a (level, estimator) never touched before overwrites its device sums
+        std::vector<SlotDev> res;
+        const mlmc_status s = run_works(ctx, works, n_sums, res);
+        if (s != MLMC_OK) return s;
+        std::vector<bool> counted(opts.size(), false);
+        for (size_t k = 0; k < works.size(); ++k) {
+            OptionRun& o = *opts[who[k].first];
+            const Pending& p = who[k].second;
+            o.sums[p.level][p.est] = res[k];
+            o.path_steps += p.n << p.level;
+            if (!counted[who[k].first]) { o.sweeps += 1; counted[who[k].first] = true; }
+        }
+        for (OptionRun* o : opts) {
+            o->saturations = 0;
+            for (auto& a : o->sums) for (auto& s : a) o->saturations += s.sat;
+        }
+    }
+}
+
+mlmc_status validate_run(const mlmc_problem* prob, const mlmc_run_config* cfg, std::string& err) {
+    mlmc_status s = validate_problem(prob, err);
+    if (s != MLMC_OK) return s;
+    if (popcount32(prob->payoff_mask) != 1) { err = "an estimate prices exactly one payoff"; return MLMC_E_INVALID; }
+    if (!cfg) { err = "run config is NULL"; return MLMC_E_INVALID; }
+    if (cfg->struct_size != sizeof(mlmc_run_config)) { err = "mlmc_run_config.struct_size mismatch"; return MLMC_E_VERSION; }
+    if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps)) { err = "eps must be > 0"; return MLMC_E_INVALID; }
+    if (!(cfg->theta > 0.0 && cfg->theta <= 1.0)) { err = "theta must be in (0, 1]"; return MLMC_E_INVALID; }
+    if (cfg->L_min < 0 || cfg->L_max < cfg->L_min || cfg->L_max >= MLMC_MAX_LEVELS) { err = "need 0 <= L_min <= L_max <= 20"; return MLMC_E_INVALID; }
+    if (cfg->n_pilot < 2) { err = "n_pilot must be >= 2"; return MLMC_E_INVALID; }
+    if (!(cfg->cost_plain > 0 && cfg->cost_approx > 0 && cfg->cost_corr > 0)) { err = "costs must be > 0"; return MLMC_E_INVALID; }
+    if (cfg->eps_units != 0 && cfg->eps_units != 1) { err = "eps_units must be 0 or 1"; return MLMC_E_INVALID; }
+    if (cfg->nested) {
+        for (int l = 0; l <= cfg->L_max; ++l) {
+            if ((s = validate_precision(&cfg->prec[l], MLMC_EST_APPROX, prob, err)) != MLMC_OK) return s;
+            mlmc_precision c = cfg->prec[l];
+            c.packed = 0;
+            if ((s = validate_precision(&c, MLMC_EST_CORR, prob, err)) != MLMC_OK) return s;
+        }
+    } else if (cfg->plain_arith != MLMC_ARITH_FP64 && cfg->plain_arith != MLMC_ARITH_FP32) {
+        err = "plain_arith must be FP64 or FP32";
+        return MLMC_E_INVALID;
+    }
+    return MLMC_OK;
+}
+
+mlmc_status estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* probs,
+                           const mlmc_run_config* cfg, uint64_t seed, const uint32_t* ids,
+                           mlmc_result* out) {
+    if (!ctx) return MLMC_E_INVALID;
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    if (!probs || !out || !ids || n == 0) return fail(ctx, MLMC_E_INVALID, "empty batch or NULL pointer");
+    std::string err;
+    for (uint32_t i = 0; i < n; ++i) {
+        const mlmc_status s = validate_run(&probs[i], cfg, err);
+        if (s != MLMC_OK) return fail(ctx, s, "option " + std::to_string(i) + ": " + err);
+    }
+    const uint32_t per = static_cast<uint32_t>(cfg->L_max + 1) * 3u;
+    std::vector<OptionRun> runs(n);
+    std::vector<OptionRun*> ptrs(n);
+    const double t0 = now_seconds();
+    for (uint32_t i = 0; i < n; ++i) {
+        runs[i].prob = probs[i];
+        runs[i].cfg = *cfg;
+        runs[i].seed = seed;
+        runs[i].option = ids[i];
+        runs[i].sums_base = i * per;
+        option_init(runs[i]);
+        runs[i].t_start = t0;
+        ptrs[i] = &runs[i];
+    }
+    const mlmc_status s = run_sweeps(ctx, ptrs, n * per);
+    if (s != MLMC_OK) return s;
+    for (uint32_t i = 0; i < n; ++i) option_result(runs[i], out[i]);
+    return MLMC_OK;
+}
+
+
+}  // namespace mlmc
+
+using namespace mlmc;
+
+// ====================================================================== ABI
+extern "C" {
+
+int32_t mlmc_abi_version(void) { return MLMC_ABI_VERSION; }
+
+const char* mlmc_status_string(int32_t s) {
+    switch (s) {
+        case MLMC_OK: return "ok";
+        case MLMC_PENDING: return "pending";
+        case MLMC_E_INVALID: return "invalid argument";
+        case MLMC_E_NOMEM: return "workspace too small";
+        case MLMC_E_DEVICE: return "device error";
+        case MLMC_E_OVERFLOW: return "fixed-point overflow";
+        case MLMC_E_BUSY: return "server busy or not running";
+        case MLMC_E_TIMEOUT: return "timeout";
+        case MLMC_E_UNKNOWN_TICKET: return "unknown ticket";
+        case MLMC_E_VERSION: return "struct_size mismatch";
+        default: return "unknown status";
+    }
+}
+
+const char* mlmc_last_error(const mlmc_context* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t workspace_bytes, void* stream,
+                                mlmc_context** out) {
+    if (!out) return MLMC_E_INVALID;
+    *out = nullptr;
+    if (workspace_bytes < (uint64_t(1) << 20)) return MLMC_E_INVALID;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MLMC_E_DEVICE;
+    if (device < 0 || device >= n) return MLMC_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return MLMC_E_DEVICE;
+    auto* ctx = new mlmc_context();
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->ws_bytes = workspace_bytes;
+    if (hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        delete ctx;
+        return MLMC_E_DEVICE;
+    }
+    if (workspace) {
+        ctx->ws = static_cast<uint8_t*>(workspace);
+    } else {
+        if (hipMalloc(reinterpret_cast<void**>(&ctx->ws), workspace_bytes) != hipSuccess) {
+            delete ctx;
+            return MLMC_E_NOMEM;
+        }
+        ctx->own_ws = true;
+    }
+    *out = ctx;
+    return MLMC_OK;
+}
+
+void mlmc_context_destroy(mlmc_context* ctx) {
+    if (!ctx) return;
+    mlmc_server_stop(ctx);
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+}
+
+mlmc_status mlmc_level_sums(mlmc_context* ctx, const mlmc_problem* prob, int32_t level, uint64_t n_paths,
+                            uint64_t path_offset, const mlmc_precision* prec, int32_t estimator, uint64_t seed,
+                            uint32_t option_id, mlmc_sums* out, void* debug_paths) {
+    if (!ctx) return MLMC_E_INVALID;
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    std::string err;
+    mlmc_status s = validate_all(prob, level, n_paths, path_offset, prec, estimator, err);
+    if (s != MLMC_OK) return fail(ctx, s, err);
+    if (!out) return fail(ctx, MLMC_E_INVALID, "out is NULL");
+    WorkSpec w;
+    w.prob = prob;
+    w.level = level;
+    w.prec = prec;
+    w.est = estimator;
+    w.seed = seed;
+    w.option = option_id;
+    w.path_begin = path_offset;
+    w.n = n_paths;
+    w.sums = 0;
+    w.debug = reinterpret_cast<uint64_t>(debug_paths);
+    w.accumulate = false;
+    std::vector<SlotDev> res;
+    s = run_works(ctx, {w}, 1, res);
+    if (s != MLMC_OK) return s;
+    const bool single = popcount32(prob->payoff_mask) == 1;
+    int i = 0;
+    for (int p = 0; p < MLMC_NPAYOFF; ++p)
+        if ((prob->payoff_mask >> p) & 1u) slot_to_sums(res[0], single ? 0 : p, out[i++]);
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works) {
+    if (!ctx) return MLMC_E_INVALID;
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    if (!works || n == 0) return fail(ctx, MLMC_E_INVALID, "empty work list");
+    std::vector<WorkSpec> ws(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const mlmc_level_work& w = works[i];
+        if (w.struct_size != sizeof(mlmc_level_work)) return fail(ctx, MLMC_E_VERSION, "mlmc_level_work.struct_size mismatch");
+        std::string err;
+        const mlmc_status s = validate_all(w.prob, w.level, w.n_paths, w.path_offset, w.prec, w.estimator, err);
+        if (s != MLMC_OK) return fail(ctx, s, "work " + std::to_string(i) + ": " + err);
+        if (!w.out) return fail(ctx, MLMC_E_INVALID, "work " + std::to_string(i) + ": out is NULL");
+        ws[i] = WorkSpec{w.prob, w.level, w.prec, w.estimator, w.seed, w.option_id, w.path_offset,
+                         w.n_paths, i, 0, false};
+    }
+    std::vector<SlotDev> res;
+    const mlmc_status s = run_works(ctx, ws, n, res);
+    if (s != MLMC_OK) return s;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t mask = works[i].prob->payoff_mask;
+        const bool single = popcount32(mask) == 1;
+        int j = 0;
+        for (int p = 0; p < MLMC_NPAYOFF; ++p)
+            if ((mask >> p) & 1u) slot_to_sums(res[i], single ? 0 : p, works[i].out[j++]);
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_set_timing(mlmc_context* ctx, int32_t on) {
+    if (!ctx) return MLMC_E_INVALID;
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    ctx->timing = on != 0;
+    ctx->stats.clear();
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_kernel_stats(mlmc_context* ctx, mlmc_kernel_stat* out, uint32_t max, uint32_t* n) {
+    if (!ctx || !n || (max && !out)) return MLMC_E_INVALID;
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    *n = static_cast<uint32_t>(ctx->stats.size());
+    for (uint32_t i = 0; i < max && i < ctx->stats.size(); ++i) out[i] = ctx->stats[i];
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_estimate(mlmc_context* ctx, const mlmc_problem* prob, const mlmc_run_config* cfg, uint64_t seed,
+                          uint32_t option_id, mlmc_result* out) {
+    return estimate_batch(ctx, 1, prob, cfg, seed, &option_id, out);
+}
+
+mlmc_status mlmc_estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* probs,
+                                const mlmc_run_config* cfg, uint64_t seed, mlmc_result* out) {
+    std::vector<uint32_t> ids(n);
+    for (uint32_t i = 0; i < n; ++i) ids[i] = i;
+    return estimate_batch(ctx, n, probs, cfg, seed, ids.data(), out);
+}
+
+// ------------------------------------------------------------- host helpers
+mlmc_status mlmc_build_table(int32_t q, int32_t arith, int32_t frac_bits, void* out) {
+    std::string err;
+    return build_table_bytes(q, arith, frac_bits, out, err);
+}
+
+mlmc_status mlmc_stream_words(uint64_t seed, uint32_t option_id, int32_t level, int32_t estimator,
+                              uint64_t word_index, uint64_t count, uint32_t* out) {
+    if (!out || level < 0 || level > 255 || estimator < 0 || estimator > 255) return MLMC_E_INVALID;
+    for (uint64_t i = 0; i < count; ++i) {
+        const uint64_t w = word_index + i;
+        const uint64_t b = w >> 2;
+        const u32x4 r = philox4x32_10(u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32),
+                                            stream_c2(level, estimator), option_id},
+                                      static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+        const uint32_t words[4] = {r.x, r.y, r.z, r.w};
+        out[i] = words[w & 3];
+    }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_validate(const mlmc_problem* prob, int32_t level, uint64_t n_paths, uint64_t path_offset,
+                          const mlmc_precision* prec, int32_t estimator) {
+    std::string err;
+    return validate_all(prob, level, n_paths, path_offset, prec, estimator, err);
+}
+
+mlmc_status mlmc_allocate(uint32_t m, const double* V, const double* C, double eps2, double theta, uint64_t* out) {
+    if (!V || !C || !out || m == 0 || !(eps2 > 0) || !(theta > 0 && theta <= 1)) return MLMC_E_INVALID;
+    double lam = 0.0;
+    for (uint32_t i = 0; i < m; ++i) {
+        if (!(V[i] >= 0) || !(C[i] > 0)) return MLMC_E_INVALID;
+        lam += std::sqrt(V[i] * C[i]);
+    }
+    lam /= theta * eps2;
+    for (uint32_t i = 0; i < m; ++i) {
+        const double t = std::ceil(lam * std::sqrt(V[i] / C[i]));
+        out[i] = t > 1.8e19 ? UINT64_MAX : static_cast<uint64_t>(t);
+    }
+    return MLMC_OK;
+}
+
+}  // extern "C"

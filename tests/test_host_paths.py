@@ -1,0 +1,38 @@
+"""The kernels' per-path code compiled for the host (mlmc_check_paths_host) against
+the oracle, with the same bars as the GPU parity tests (tests/parity.py), without a
+GPU.  This pins the kernel arithmetic; the GPU tests add launch, tiling, reductions."""
+import numpy as np
+import pytest
+
+import paper_2502_07123_amd as M
+from oracle.paths import Precision, Problem, simulate
+from parity import CASES, GBM, PAYS, SEED, WIDE_FMT, case_q, check_records, oracle_run
+
+
+@pytest.mark.parametrize("level", [0, 1, 3, 6])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(map(str, c)))
+def test_host_paths_match_oracle(case, level):
+    scheme, est, arith, packed = case
+    n, off = 700, 33
+    prob = M.make_problem(scheme, PAYS, **GBM)
+    prec = M.make_precision(arith, case_q(case), packed, WIDE_FMT)
+    sums, rec = M.check_paths_host(prob, level, n, off, prec, est, SEED)
+    o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS)
+    check_records(case, level, n, off, PAYS, sums, rec, o)
+
+
+def test_host_narrow_fixed_counts_saturations():
+    """A format too narrow for X saturates; the per-path counts match the oracle's."""
+    fmt = dict(WIDE_FMT)
+    fmt["X"] = (8, 6)
+    fmt["mul2"] = (12, 10)
+    prob = M.make_problem("euler", ("euro",), **GBM)
+    prec = M.make_precision("fixed", 8, False, fmt)
+    sums, rec = M.check_paths_host(prob, 4, 3000, 0, prec, M.EST_APPROX, SEED)
+    o = simulate(Problem("euler", **GBM), 4, np.arange(3000, dtype=np.uint64),
+                 Precision("fixed", 8, False, tuple((v, w, f) for v, (w, f) in fmt.items())),
+                 M.EST_APPROX, SEED)
+    assert o["sat"].sum() > 0
+    assert np.array_equal(rec["saturations"], o["sat"])
+    assert sums["euro"]["saturations"] == int(o["sat"].sum())
+    assert np.array_equal(rec["XN_raw"], o["XN_approx"])
