@@ -35,7 +35,7 @@ N_PILOT = 100_000
 # class.  Philox4x32-10: 10 rounds of 2 widening 32x32->64 multiplies and 4 xors
 # per block of 4 words; each multiply is weighted by its issue cost relative to a
 # full-rate 32-bit op (MUL64_COST, measured on gfx950 by the instruction probe).
-MUL64_COST = 4.0
+MUL64_COST = 2.0      # v_mad_u64_u32 issues at half the FP32 rate (probe: 49 vs 98 lanes/CU/clk)
 
 
 def philox_ops():
@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tte", action="store_true", help="skip the time-to-eps comparison")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 256 MiB device-to-device (a known-size kernel that scales "
+                         "the HBM byte counters of a profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -121,6 +124,12 @@ def main():
     import torch
     import paper_2502_07123_amd as M
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = M.Context(0, workspace_bytes=1 << 30)
     prob = M.make_problem("milstein", ("euro",), **GBM)
     prec_a = M.make_precision("fp32", Q, packed=True)
@@ -128,13 +137,11 @@ def main():
     scale = math.exp(-GBM["r"] * GBM["T"]) * GBM["S0"]
     eps_int = EPS / scale
 
-    # pilot + cost calibration (untimed): variances and ns per path-step per estimator
-    ctx.set_timing(True)
+    # cost model (R11: per-estimator ns per fine path-step, frozen for the run) from
+    # large launches, then the pilot for the variances (all untimed)
+    c_a, c_c, c_p = calibrate(M, ctx, prob, prec_a, prec_c)
     pil = ctx.level_sums_batch(make_items(M, prob, prec_a, prec_c, [N_PILOT] * LEVELS,
                                           [N_PILOT] * LEVELS, 0))
-    stats = ctx.kernel_stats()
-    ns = {s["estimator"]: s["ms"] * 1e6 / s["path_steps"] for s in stats}
-    c_a, c_c = ns[M.EST_APPROX], ns[M.EST_CORR]
 
     def var(s):
         n = s["n"]
@@ -195,7 +202,7 @@ def main():
                      "path_steps_per_s": s["path_steps"] / (s["ms"] * 1e-3)} for s in stats],
     }
     if not args.no_tte:
-        extra["time_to_eps"] = time_to_eps(M, ctx, prob, prec_a, c_a, c_c)
+        extra["time_to_eps"] = time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p)
     cpu = None if args.no_cpu else cpu_baseline(Na, Nc)
     line = {
         "metric": "path-steps/s per level; time to RMSE eps, nested low-prec vs plain FP32",
@@ -212,18 +219,27 @@ def main():
     ctx.close()
 
 
-def time_to_eps(M, ctx, prob, prec_a, c_a, c_c):
+def calibrate(M, ctx, prob, prec_a, prec_c, level=4, n=1 << 22):
+    """ns per fine path-step of the approximate, correction and plain-FP32 kernels,
+    from one large launch each (after a warm-up launch)."""
+    out = []
+    for est, prec in ((M.EST_APPROX, prec_a), (M.EST_CORR, prec_c),
+                      (M.EST_PLAIN, M.make_precision("fp32", Q))):
+        ctx.level_sums(prob, level, n, 0, prec, est, SEED + 99)
+        ctx.set_timing(True)
+        ctx.level_sums(prob, level, n, n, prec, est, SEED + 99)
+        st = ctx.kernel_stats()[0]
+        ctx.set_timing(False)
+        out.append(st["ms"] * 1e6 / st["path_steps"])
+    return tuple(out)
+
+
+def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p):
     """Wall time of one on-line MLMC estimate to RMSE eps (price units), levels 0..8,
     nested (FP32 table + FP64 correction) vs plain FP32 (exact FP32 normals); the
     cost model uses the calibrated ns per path-step of each kernel class."""
     import numpy as np
     out = {}
-    plain_stat = {}
-    ctx.set_timing(True)
-    ctx.level_sums(prob, 4, 200_000, 0, M.make_precision("fp32", Q), M.EST_PLAIN, SEED)
-    st = ctx.kernel_stats()
-    ctx.set_timing(False)
-    c_p = st[0]["ms"] * 1e6 / st[0]["path_steps"]
     for name, nested in (("nested", True), ("plain_fp32", False)):
         cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", theta=1.0, L_min=8, L_max=8,
                                 n_pilot=20_000, costs=(c_p, c_a, c_c), plain_arith="fp32",

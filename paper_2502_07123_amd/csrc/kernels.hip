@@ -8,8 +8,8 @@
 // fixed order -- butterfly within each 64-lane wave, then waves in index order --
 // into the tile's own slot.  Results therefore do not depend on which block ran a
 // tile or on what else was in the launch.
-// k_reduce: one block per work item; thread f adds field f of the item's tile
-// slots sequentially in tile order (optionally onto the running total).
+// k_reduce: one block per work item adds the item's tile slots in a fixed order
+// (optionally onto the running total).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -151,51 +151,106 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
     }
 }
 
-__global__ void __launch_bounds__(64)
+// Sums of one work's tile slots in a fixed order: thread t adds slots t, t + B,
+// t + 2B, ... (B = 256), then a butterfly within each wave and the waves in index
+// order, onto the running total when accumulating.
+struct RedAcc {
+    double d[4 * NPAY];
+    int64_t i1[NPAY];
+    uint64_t lo[NPAY], hi[NPAY];
+    uint64_t c[3];
+};
+
+__device__ __forceinline__ void red_zero(RedAcc& a) {
+#pragma unroll
+    for (int i = 0; i < 4 * NPAY; ++i) a.d[i] = 0.0;
+#pragma unroll
+    for (int p = 0; p < NPAY; ++p) { a.i1[p] = 0; a.lo[p] = 0; a.hi[p] = 0; }
+    a.c[0] = a.c[1] = a.c[2] = 0;
+}
+
+__device__ __forceinline__ void add128(uint64_t& lo, uint64_t& hi, uint64_t blo, uint64_t bhi) {
+    const uint64_t nlo = lo + blo;
+    hi += bhi + (nlo < lo ? 1u : 0u);
+    lo = nlo;
+}
+
+__device__ __forceinline__ void red_add(RedAcc& a, const SlotDev& s) {
+#pragma unroll
+    for (int p = 0; p < NPAY; ++p) {
+        a.d[p] += s.s1[p];
+        a.d[NPAY + p] += s.s2[p];
+        a.d[2 * NPAY + p] += s.e1[p];
+        a.d[3 * NPAY + p] += s.e2[p];
+        a.i1[p] += s.i1[p];
+        add128(a.lo[p], a.hi[p], s.i2lo[p], s.i2hi[p]);
+    }
+    a.c[0] += s.n;
+    a.c[1] += s.sat;
+    a.c[2] += s.nonfinite;
+}
+
+__device__ __forceinline__ void red_add(RedAcc& a, const RedAcc& b) {
+#pragma unroll
+    for (int i = 0; i < 4 * NPAY; ++i) a.d[i] += b.d[i];
+#pragma unroll
+    for (int p = 0; p < NPAY; ++p) { a.i1[p] += b.i1[p]; add128(a.lo[p], a.hi[p], b.lo[p], b.hi[p]); }
+    a.c[0] += b.c[0];
+    a.c[1] += b.c[1];
+    a.c[2] += b.c[2];
+}
+
+__device__ __forceinline__ void red_wave(RedAcc& a) {
+#pragma unroll
+    for (int i = 0; i < 4 * NPAY; ++i) a.d[i] = wave_sum(a.d[i]);
+#pragma unroll
+    for (int p = 0; p < NPAY; ++p) {
+        a.i1[p] = wave_sum(a.i1[p]);
+        wave_sum128(a.lo[p], a.hi[p]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a.c[i] = static_cast<uint64_t>(wave_sum(static_cast<int64_t>(a.c[i])));
+}
+
+constexpr int REDUCE_THREADS = 256;
+
+__global__ void __launch_bounds__(REDUCE_THREADS)
 k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, uint32_t n,
          SlotDev* __restrict__ sums, SlotDev* __restrict__ compact) {
+    __shared__ RedAcc part[REDUCE_THREADS / 64];
     const uint32_t w = blockIdx.x;
     if (w >= n) return;
     const ReduceDev rd = rds[w];
     SlotDev* dst = &sums[rd.sums];
-    const int f = threadIdx.x;
-    if (f < 4 * NPAY) {
-        const int which = f / NPAY, p = f % NPAY;
-        double* d = (which == 0 ? dst->s1 : which == 1 ? dst->s2 : which == 2 ? dst->e1 : dst->e2) + p;
-        const size_t off = reinterpret_cast<const uint8_t*>(d) - reinterpret_cast<const uint8_t*>(dst);
-        double acc = rd.accumulate ? *d : 0.0;
-        for (uint32_t s = rd.slot_begin; s < rd.slot_end; ++s)
-            acc += *reinterpret_cast<const double*>(reinterpret_cast<const uint8_t*>(&slots[s]) + off);
-        *d = acc;
-    } else if (f < 5 * NPAY) {
-        const int p = f - 4 * NPAY;
-        int64_t acc = rd.accumulate ? dst->i1[p] : 0;
-        for (uint32_t s = rd.slot_begin; s < rd.slot_end; ++s) acc += slots[s].i1[p];
-        dst->i1[p] = acc;
-    } else if (f < 6 * NPAY) {
-        const int p = f - 5 * NPAY;
-        uint64_t lo = rd.accumulate ? dst->i2lo[p] : 0, hi = rd.accumulate ? dst->i2hi[p] : 0;
-        for (uint32_t s = rd.slot_begin; s < rd.slot_end; ++s) {
-            const uint64_t nlo = lo + slots[s].i2lo[p];
-            hi += slots[s].i2hi[p] + (nlo < lo ? 1u : 0u);
-            lo = nlo;
-        }
-        dst->i2lo[p] = lo;
-        dst->i2hi[p] = hi;
-    } else if (f < 6 * NPAY + 3) {
-        const int c = f - 6 * NPAY;
-        uint64_t acc = rd.accumulate ? (c == 0 ? dst->n : c == 1 ? dst->sat : dst->nonfinite) : 0;
-        for (uint32_t s = rd.slot_begin; s < rd.slot_end; ++s)
-            acc += c == 0 ? slots[s].n : c == 1 ? slots[s].sat : slots[s].nonfinite;
-        if (c == 0) dst->n = acc;
-        else if (c == 1) dst->sat = acc;
-        else dst->nonfinite = acc;
-    }
+    RedAcc a;
+    red_zero(a);
+    for (uint32_t s = rd.slot_begin + threadIdx.x; s < rd.slot_end; s += blockDim.x) red_add(a, slots[s]);
+    red_wave(a);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) part[wave] = a;
     __syncthreads();
-    // copy the updated sums for the host (one 8-byte word per thread)
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(dst);
-    uint64_t* cp = reinterpret_cast<uint64_t*>(&compact[w]);
-    for (uint32_t i = threadIdx.x; i < sizeof(SlotDev) / 8; i += blockDim.x) cp[i] = src[i];
+    if (threadIdx.x == 0) {
+        RedAcc t;
+        red_zero(t);
+        if (rd.accumulate) red_add(t, *dst);
+        for (int v = 0; v < static_cast<int>(blockDim.x >> 6); ++v) red_add(t, part[v]);
+        SlotDev o;
+        for (int p = 0; p < NPAY; ++p) {
+            o.s1[p] = t.d[p];
+            o.s2[p] = t.d[NPAY + p];
+            o.e1[p] = t.d[2 * NPAY + p];
+            o.e2[p] = t.d[3 * NPAY + p];
+            o.i1[p] = t.i1[p];
+            o.i2lo[p] = t.lo[p];
+            o.i2hi[p] = t.hi[p];
+        }
+        o.n = t.c[0];
+        o.sat = t.c[1];
+        o.nonfinite = t.c[2];
+        o.pad = 0;
+        *dst = o;
+        compact[w] = o;
+    }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -234,7 +289,7 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
                          SlotDev* sums, SlotDev* compact) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(n), dim3(64), 0, st, slots, rds, n, sums, compact);
+    hipLaunchKernelGGL(k_reduce, dim3(n), dim3(REDUCE_THREADS), 0, st, slots, rds, n, sums, compact);
     return hipGetLastError();
 }
 

@@ -157,9 +157,17 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
             const uint64_t G = S >> w.level;                       // paths per group
             const uint64_t g0 = w.path_begin / G;
             const uint64_t g1 = (w.path_begin + w.n - 1) / G + 1;
-            uint64_t per = uint64_t(g.block) * std::max<uint64_t>(1, ctx->tune.tile_steps / (g.block * S));
+            // groups per tile: about tile_steps path-steps, but small enough that the work
+            // alone has min_tiles tiles (parallelism), and at most max_tiles tiles; a
+            // function of the work alone, so a work's sums do not depend on its neighbours
+            const uint64_t total = g1 - g0;
+            uint64_t ppt = std::max<uint64_t>(1, ctx->tune.tile_steps / (g.block * S));
+            const uint64_t fill = (total + uint64_t(g.block) * ctx->tune.min_tiles - 1) /
+                                  (uint64_t(g.block) * ctx->tune.min_tiles);
+            ppt = std::max<uint64_t>(1, std::min(ppt, fill));
+            uint64_t per = uint64_t(g.block) * ppt;
             const uint64_t max_tiles = 1u << 16;
-            if ((g1 - g0 + per - 1) / per > max_tiles) per = (g1 - g0 + max_tiles - 1) / max_tiles;
+            if ((total + per - 1) / per > max_tiles) per = (total + max_tiles - 1) / max_tiles;
             reds[wi].slot_begin = static_cast<uint32_t>(tiles.size());
             for (uint64_t gg = g0; gg < g1; gg += per) {
                 TileDev t;

@@ -28,6 +28,7 @@ struct Tuning {
     uint32_t block_exact = 256;     // threads per block, kernels with exact normals
     uint32_t tile_steps = 1u << 16; // path-steps per tile (target)
     uint32_t blocks_per_cu = 8;     // persistent grid = CUs * blocks_per_cu (cap)
+    uint32_t min_tiles = 2048;      // a work is split into at least this many tiles when it can be
 };
 
 // One (option, level, estimator) path range of a launch.

@@ -1,0 +1,153 @@
+"""The C-ABI library on the CPU (no GPU calls): it loads, exports every entry
+point that include/mlmc.h declares, its structs have the header's layout, the
+validation rules of the header hold, and its host helpers (Method-1 table
+builder, uniform stream, allocation) equal the oracle."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import paper_2502_07123_amd as M
+from paper_2502_07123_amd import _lib
+from oracle import normal, philox
+from oracle.mlmc import optimal_samples
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlmc.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlmc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = header_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(_lib.EXPORTED) <= set(declared)
+    assert L.mlmc_abi_version() == _lib.ABI_VERSION
+
+
+STRUCTS = {"mlmc_problem": _lib.Problem, "mlmc_precision": _lib.Precision, "mlmc_sums": _lib.Sums,
+           "mlmc_level_work": _lib.LevelWork, "mlmc_kernel_stat": _lib.KernelStat,
+           "mlmc_run_config": _lib.RunConfig, "mlmc_level_stats": _lib.LevelStats,
+           "mlmc_result": _lib.Result, "mlmc_server_config": _lib.ServerConfig,
+           "mlmc_request": _lib.Request}
+
+
+def test_struct_layouts_match_the_header():
+    d = tempfile.mkdtemp(prefix="mlmc_abi_")
+    src = os.path.join(d, "s.c")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for s in STRUCTS:
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+    lines.append('printf("rec %zu\\n", sizeof(mlmc_path_record));')
+    lines.append('printf("off_run_prec %zu\\n", offsetof(mlmc_run_config, prec));')
+    lines.append('printf("off_res_level %zu\\n", offsetof(mlmc_result, level));')
+    lines.append("return 0;}")
+    open(src, "w").write("\n".join(lines))
+    exe = os.path.join(d, "s")
+    subprocess.run(["gcc", "-std=c99", src, "-o", exe], check=True)
+    out = dict(l.split() for l in subprocess.run([exe], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for s, cls in STRUCTS.items():
+        assert int(out[s]) == C.sizeof(cls), s
+    assert int(out["rec"]) == M.RECORD_DTYPE.itemsize
+    assert int(out["off_run_prec"]) == _lib.RunConfig.prec.offset
+    assert int(out["off_res_level"]) == _lib.Result.level.offset
+
+
+GBM = dict(S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, barrier=85.0)
+
+
+def _ok_prec(arith="fp32", q=8, packed=False):
+    fmt = {"X": (32, 29), "con1": (32, 34), "con2": (32, 33), "con3": (32, 36), "Z": (31, 28),
+           "mul1": (32, 30), "sum1": (32, 30), "zsq": (32, 23), "zm1": (32, 23),
+           "mul3": (32, 29), "sum2": (32, 29), "mul2": (32, 27)}
+    return M.make_precision(arith, q, packed, fmt)
+
+
+def test_validation_rules():
+    INVALID, VERSION = -1, -8
+    p = M.make_problem("milstein", ("euro", "barrier"), **GBM)
+    assert M.validate(p, 3, 1000, 0, _ok_prec(), M.EST_APPROX) == 0
+    assert M.validate(p, 3, 1000, 0, _ok_prec("fixed"), M.EST_CORR) == 0
+    assert M.validate(p, 21, 1000, 0, _ok_prec(), M.EST_APPROX) == INVALID     # level
+    assert M.validate(p, 3, 0, 0, _ok_prec(), M.EST_APPROX) == INVALID         # n_paths
+    assert M.validate(p, 3, 10, 2 ** 40, _ok_prec(), M.EST_APPROX) == INVALID  # range
+    assert M.validate(p, 3, 10, 0, _ok_prec(), 3) == INVALID                   # estimator
+    bad = M.make_problem("milstein", ("euro",), **{**GBM, "sigma": -0.2})
+    assert M.validate(bad, 3, 10, 0, _ok_prec(), M.EST_APPROX) == INVALID
+    bad = M.make_problem("milstein", ("barrier",), **{**GBM, "barrier": 120.0})
+    assert M.validate(bad, 3, 10, 0, _ok_prec(), M.EST_APPROX) == INVALID      # barrier >= S0
+    bad = M.make_problem("milstein", ("euro",), **GBM)
+    bad.payoff_mask = 0
+    assert M.validate(bad, 3, 10, 0, _ok_prec(), M.EST_APPROX) == INVALID
+    bad = M.make_problem("milstein", ("euro",), **GBM)
+    bad.struct_size = 8
+    assert M.validate(bad, 3, 10, 0, _ok_prec(), M.EST_APPROX) == VERSION
+    assert M.validate(p, 3, 10, 0, _ok_prec(q=0), M.EST_APPROX) == INVALID      # q
+    assert M.validate(p, 3, 10, 0, _ok_prec(q=13), M.EST_APPROX) == INVALID
+    assert M.validate(p, 3, 10, 0, _ok_prec(packed=True), M.EST_CORR) == INVALID
+    assert M.validate(p, 3, 10, 0, _ok_prec(q=5, packed=True), M.EST_APPROX) == INVALID
+    assert M.validate(p, 3, 10, 0, _ok_prec("fp16"), M.EST_APPROX) == INVALID
+    assert M.validate(p, 3, 10, 0, _ok_prec("fixed"), M.EST_PLAIN) == INVALID
+    pr = _ok_prec("fixed")
+    pr.frac_bits[_lib.VARS.index("mul2")] = 62                               # f_dst > f_a + f_b
+    assert M.validate(p, 3, 10, 0, pr, M.EST_APPROX) == INVALID
+    pr = _ok_prec("fixed")
+    pr.word_bits[_lib.VARS.index("Z")] = 32                                  # Z at most 31 bits
+    assert M.validate(p, 3, 10, 0, pr, M.EST_APPROX) == INVALID
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert L.mlmc_status_string(code).decode() not in ("", "unknown status")
+    assert L.mlmc_status_string(99).decode() == "unknown status"
+
+
+def test_context_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = C.c_void_p()
+    st = _lib.lib().mlmc_context_create(0, None, 1 << 24, None, C.byref(h))
+    assert st in (-3, -1) and not h.value
+
+
+@pytest.mark.parametrize("q", [1, 2, 4, 6, 8, 10, 12])
+def test_table_builder_equals_oracle(q):
+    assert np.array_equal(M.build_table(q, "fp32"), normal.table_float(q, "float32"))
+    h = M.build_table(q, "fp16")
+    assert np.array_equal(h.view(np.float16), normal.table_float(q, "float16"))
+    for f in (12, 20, 28):
+        assert np.array_equal(M.build_table(q, "fixed", f), normal.table_fixed(q, f))
+    d = M.build_table(q, "fp64")
+    ref = np.array([float(t) for t in normal.table_exact(q)])
+    assert np.allclose(d, ref, rtol=1e-15, atol=1e-17)
+
+
+def test_stream_words_equal_oracle():
+    for (seed, opt, lvl, est, w0) in ((1234, 0, 0, 0, 0), (2 ** 40 + 7, 9, 10, 2, 2 ** 35 + 3)):
+        got = M.stream_words(seed, opt, lvl, est, w0, 257)
+        ref = philox.stream_words(seed, opt, lvl, est, np.arange(w0, w0 + 257, dtype=np.uint64))
+        assert np.array_equal(got, ref)
+
+
+def test_allocation_equals_oracle():
+    V = np.array([1e-2, 3e-4, 8e-5, 2e-5, 5e-6, 1e-6])
+    Cst = np.array([1.0, 2, 4, 8, 16, 32]) * 0.37
+    for theta in (1.0, 0.5):
+        got = M.allocate(V, Cst, 1e-7, theta)
+        ref = optimal_samples(V, Cst, 1e-7, theta)
+        assert np.array_equal(got.astype(np.int64), ref)
