@@ -16,7 +16,9 @@ the finer operand) is rounded once to the destination f, then saturated.
 
 `exact_*` functions do the same with fractions.Fraction scalars (the definition);
 the numpy versions (int64, |operands| < 2^31) are the ones the paths use and are
-tested equal to the Fraction versions.
+tested equal to the Fraction versions on their domain: a product keeps at most
+its own fractional bits (f_dst <= f_a + f_b) and a sum at most its finer operand's
+(f_dst <= max(f_a, f_b)) with |f_a - f_b| <= 30, so no intermediate exceeds 2^62.
 
 This module is test infrastructure: see the package docstring.
 """

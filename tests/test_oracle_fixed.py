@@ -53,6 +53,7 @@ fr = st.integers(0, 30)
 @settings(max_examples=400, deadline=None)
 @given(i32, i32, fr, fr, fr, st.integers(2, 32))
 def test_mul_32bit(a, b, fa, fb, fd, wd):
+    fd = min(fd, fa + fb)                    # the operation's domain (module docstring)
     got, sat = fx.mul(np.array([a]), fa, np.array([b]), fb, fd, wd)
     assert (int(got[0]), int(sat[0])) == fx.exact_mul(a, fa, b, fb, fd, wd)
 
@@ -60,6 +61,7 @@ def test_mul_32bit(a, b, fa, fb, fd, wd):
 @settings(max_examples=400, deadline=None)
 @given(i32, i32, fr, fr, fr, st.integers(2, 32), st.booleans())
 def test_add_32bit(a, b, fa, fb, fd, wd, sub):
+    fd = min(fd, max(fa, fb))                # the operation's domain (module docstring)
     got, sat = fx.add(np.array([a]), fa, np.array([b]), fb, fd, wd, sub=sub)
     assert (int(got[0]), int(sat[0])) == fx.exact_add(a, fa, b, fb, fd, wd, sub=sub)
 
