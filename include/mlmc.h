@@ -215,6 +215,30 @@ typedef struct mlmc_kernel_stat {
     uint64_t path_steps;                       /* fine path-steps (paths * 2^level) */
 } mlmc_kernel_stat;
 
+/* Launch geometry of a context.  Results are reproducible for a fixed tuning;
+ * FP64 sums may change in the last bits when it changes (summation order), integer
+ * sums never do.  Defaults: 256, 256, 65536, 8, 2048, 32768, 4194304.
+ *   block_table   threads per block of the table-only (APPROX) kernels, 64..1024
+ *   block_exact   threads per block of kernels with exact normals, 64..256
+ *   tile_steps    target fine path-steps per tile
+ *   blocks_per_cu persistent grid = CUs * blocks_per_cu
+ *   min_tiles     a work is split into at least this many tiles when it can be
+ *   zb_max_paths, zb_max_positions: exact-normal works (levels >= 2) with at most
+ *                 this many paths and paths*2^level stream positions get their
+ *                 normals computed ahead by a separate kernel (off the paths'
+ *                 sequential chains); 0 disables. */
+typedef struct mlmc_tuning {
+    uint32_t struct_size;
+    uint32_t block_table, block_exact;
+    uint32_t tile_steps;
+    uint32_t blocks_per_cu;
+    uint32_t min_tiles;
+    uint64_t zb_max_paths, zb_max_positions;
+} mlmc_tuning;
+
+mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out);
+mlmc_status mlmc_set_tuning(mlmc_context* ctx, const mlmc_tuning* t);   /* MLMC_E_INVALID if out of range */
+
 mlmc_status mlmc_set_timing(mlmc_context* ctx, int32_t on);  /* also clears the stats */
 /* Copies up to max stats into out (host); *n receives the number available. */
 mlmc_status mlmc_kernel_stats(mlmc_context* ctx, mlmc_kernel_stat* out, uint32_t max, uint32_t* n);

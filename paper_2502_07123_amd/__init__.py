@@ -11,7 +11,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, PAYOFFS, RECORD_DTYPE, VARS, KernelStat, LevelWork,
+from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, PAYOFFS, RECORD_DTYPE, VARS, KernelStat, LevelWork, Tuning,
                    MlmcError, Problem, Precision, Request, Result, RunConfig, ServerConfig, Sums,
                    check, lib, make_precision, make_problem, make_run_config)
 
@@ -95,6 +95,19 @@ class Context:
                                  C.cast(out, C.POINTER(Sums)))
         check(lib().mlmc_level_sums_batch(self.h, n, works), self.h)
         return [{nm: out[j].as_dict() for j, nm in enumerate(names)} for names, out in outs]
+
+    def get_tuning(self):
+        t = Tuning()
+        check(lib().mlmc_get_tuning(self.h, C.byref(t)), self.h)
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Change launch geometry fields (see mlmc_tuning in include/mlmc.h)."""
+        t = Tuning()
+        check(lib().mlmc_get_tuning(self.h, C.byref(t)), self.h)
+        for k, v in kw.items():
+            setattr(t, k, v)
+        check(lib().mlmc_set_tuning(self.h, C.byref(t)), self.h)
 
     def set_timing(self, on=True):
         check(lib().mlmc_set_timing(self.h, 1 if on else 0), self.h)

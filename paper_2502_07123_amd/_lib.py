@@ -82,6 +82,15 @@ class KernelStat(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("pad")}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("block_table", C.c_uint32), ("block_exact", C.c_uint32),
+                ("tile_steps", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("min_tiles", C.c_uint32),
+                ("zb_max_paths", C.c_uint64), ("zb_max_positions", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+
+
 class RunConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("nested", C.c_int32), ("eps_units", C.c_int32),
                 ("L_min", C.c_int32), ("L_max", C.c_int32), ("plain_arith", C.c_int32),
@@ -141,6 +150,8 @@ def lib():
                                  P(Sums), vp]),
         "mlmc_level_sums_batch": (st, [vp, u32, P(LevelWork)]),
         "mlmc_set_timing": (st, [vp, i32]),
+        "mlmc_get_tuning": (st, [vp, P(Tuning)]),
+        "mlmc_set_tuning": (st, [vp, P(Tuning)]),
         "mlmc_kernel_stats": (st, [vp, P(KernelStat), u32, P(u32)]),
         "mlmc_estimate": (st, [vp, P(Problem), P(RunConfig), u64, u32, P(Result)]),
         "mlmc_estimate_batch": (st, [vp, u32, P(Problem), P(RunConfig), u64, P(Result)]),
@@ -166,6 +177,7 @@ def lib():
 
 EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_context_create",
             "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_batch", "mlmc_set_timing",
+            "mlmc_get_tuning", "mlmc_set_tuning",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_server_stop",
             "mlmc_build_table", "mlmc_stream_words", "mlmc_validate", "mlmc_check_paths_host",

@@ -53,6 +53,10 @@ struct WorkDev {
     uint32_t sums;            // index of its accumulated sums
     uint64_t path_begin, path_end;
     uint64_t debug;           // device address of mlmc_path_record[path_end - path_begin] or 0
+    // Normals computed ahead by k_normals (0: computed in the path kernel): for
+    // path i and step n, word J and exact normal Z at index n P + (i - path_begin),
+    // P = path_end - path_begin; Z has the exact side's type.
+    uint64_t zbuf, jbuf;
 };
 
 struct TileDev {

@@ -339,6 +339,180 @@ struct PathBody {
         }
     }
 
+    // One path of a work whose words and exact normals were computed ahead by
+    // k_normals (works with few, long paths: the inverse normal then leaves the
+    // path's sequential chain).  Same steps and records as run_group.
+    __host__ __device__ __forceinline__ static void run_path_buffered(const LevelDev& L,
+                                                                      const WorkDev& W,
+                                                                      uint64_t pidx, const void* tab,
+                                                                      Acc<NP>& acc) {
+        const int lev = L.level;
+        const uint32_t N = 1u << lev;
+        const uint64_t P = W.path_end - W.path_begin;
+        const uint64_t col = pidx - W.path_begin;
+        const ExactT* Zb = reinterpret_cast<const ExactT*>(W.zbuf);
+        const uint32_t* Jb = reinterpret_cast<const uint32_t*>(W.jbuf);
+        const int q = L.q;
+        FSide<ExactT> ex;
+        FSide<float> ap;
+        XSide ax;
+        ex.init();
+        if (HAS_TABLE) { if (FIXED) ax.init(L); else ap.init(); }
+        const uint32_t first_word = Jb[col];
+        const uint32_t first_index = HAS_TABLE ? (first_word >> (32 - q)) : 0u;
+        // N >= 4 for buffered works: steps come in (even, odd) pairs
+        for (uint32_t n = 0; n < N; n += 2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint64_t idx = uint64_t(n + h) * P + col;
+                const uint32_t J = Jb[idx];
+                exact_step<MIL>(ex, Zb[idx], L, true, h == 1, TRACK);
+                if (HAS_TABLE) {
+                    const uint32_t k = J >> (32 - q);
+                    if (FIXED) {
+                        const int2 e = static_cast<const int2*>(tab)[k];
+                        fixed_step<MIL>(ax, e.x, e.y, L, true, h == 1, TRACK);
+                    } else {
+                        const float2 e = static_cast<const float2*>(tab)[k];
+                        table_step<MIL>(ap, e.x, e.y, L, true, h == 1, TRACK);
+                    }
+                }
+            }
+        }
+        finish(L, W, pidx, ex, ap, ax, first_word, first_index, acc);
+    }
+
+    // The estimator's sample for payoff p from the final path states: Ye (exact side
+    // dP), Ya (approximate side dP~, FP64 view), Yint (fixed point: dP~ as an
+    // integer), Y (the estimator's sample).
+    __host__ __device__ __forceinline__ static void sample(const LevelDev& L, int p,
+                                                           const FSide<ExactT>& ex,
+                                                           const FSide<float>& ap, XSide& ax,
+                                                           ExactT ek, ExactT eb, double& Ye,
+                                                           double& Ya, int64_t& Yint, double& Y) {
+        const int lev = L.level;
+        Ye = 0.0;
+        Ya = 0.0;
+        Yint = 0;
+        if (HAS_EXACT) {
+            const ExactT pf = ex.payoff(p, true, lev, ek, eb);
+            const ExactT pc = lev ? ex.payoff(p, false, lev - 1, ek, eb) : ExactT(0);
+            Ye = static_cast<double>(pf - pc);
+        }
+        if (HAS_TABLE) {
+            if (FIXED) {
+                const int64_t pf = ax.payoff(p, true, lev, L);
+                const int64_t pc = lev ? ax.payoff(p, false, lev - 1, L) : 0;
+                Yint = pf - pc;
+                Ya = ldexp(static_cast<double>(Yint), -L.fX);
+            } else {
+                const float pf = ap.payoff(p, true, lev, L.fk, L.fb);
+                const float pc = lev ? ap.payoff(p, false, lev - 1, L.fk, L.fb) : 0.0f;
+                const float y = pf - pc;
+                Ya = static_cast<double>(y);
+            }
+        }
+        if (EST == MLMC_EST_PLAIN) Y = Ye;
+        else if (EST == MLMC_EST_APPROX) Y = Ya;
+        else Y = Ye - Ya;
+    }
+
+    // ---- level 0 of the approximate estimator as an index histogram.  A level-0
+    // path has one step, so with Method-1 normals its sample is a function of its
+    // table index k alone: sum_paths f(Y) = sum_k c_k f(Y(k)).  The kernel counts
+    // the indices of a tile and evaluates Y(k) once per index with the path code.
+    static constexpr bool HIST = EST == MLMC_EST_APPROX;
+
+    // the level-0 path of index k (its final states)
+    __host__ __device__ __forceinline__ static void level0_path(const LevelDev& L, const void* tab,
+                                                                uint32_t k, FSide<float>& ap,
+                                                                XSide& ax) {
+        if (FIXED) {
+            ax.init(L);
+            const int2 e = static_cast<const int2*>(tab)[k];
+            fixed_step<MIL>(ax, e.x, e.y, L, false, false, TRACK);
+        } else {
+            ap.init();
+            const float2 e = static_cast<const float2*>(tab)[k];
+            table_step<MIL>(ap, e.x, e.y, L, false, false, TRACK);
+        }
+    }
+
+    // Counts the indices of level-0 group g (WPB whole paths, one Philox block),
+    // calling count(k) per path in range; with a debug buffer, also writes each
+    // path's record from the per-path code.
+    template <class Count>
+    __host__ __device__ __forceinline__ static void hist_group(const LevelDev& L, const WorkDev& W,
+                                                               uint64_t g, const void* tab,
+                                                               Count& count) {
+        const uint64_t path0 = g * WPB;
+        const u32x4 r = philox4x32_10(
+            u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+        const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+        const bool full = path0 >= W.path_begin && path0 + WPB <= W.path_end;
+        const int q = L.q;
+#pragma unroll
+        for (int wi = 0; wi < 4; ++wi) {
+#pragma unroll
+            for (int fi = 0; fi < F; ++fi) {
+                const uint32_t J = wd[wi];
+                const uint32_t k =
+                    (F == 1) ? (J >> (32 - q)) : ((J >> (32 - q * (fi + 1))) & ((1u << q) - 1u));
+                const uint64_t pidx = path0 + uint64_t(wi * F + fi);
+                if (full || (pidx >= W.path_begin && pidx < W.path_end)) {
+                    count(k);
+                    if (W.debug) {
+                        FSide<ExactT> ex;
+                        FSide<float> ap;
+                        XSide ax;
+                        level0_path(L, tab, k, ap, ax);
+                        Acc<NP> scratch;
+                        acc_zero(scratch);
+                        finish(L, W, pidx, ex, ap, ax, J, k, scratch);
+                    }
+                }
+            }
+        }
+    }
+
+    // Adds c copies of the level-0 sample of index k to acc.
+    __host__ __device__ __forceinline__ static void hist_accumulate(const LevelDev& L,
+                                                                    const void* tab, uint32_t k,
+                                                                    uint32_t c, Acc<NP>& acc) {
+        FSide<ExactT> ex;
+        FSide<float> ap;
+        XSide ax;
+        level0_path(L, tab, k, ap, ax);
+        const double cd = static_cast<double>(c);
+#pragma unroll
+        for (int slot = 0; slot < NP; ++slot) {
+            const int p = NP == 1 ? L.payoff_single : slot;
+            if (NP != 1 && !((L.payoff_mask >> p) & 1u)) continue;
+            double Ye, Ya, Y;
+            int64_t Yint;
+            sample(L, p, ex, ap, ax, ExactT(0), ExactT(0), Ye, Ya, Yint, Y);
+            if (!__builtin_isfinite(Y)) { acc.nonfinite += c; continue; }
+            acc.s1[slot] = fma(cd, Y, acc.s1[slot]);            // c Y is exact
+            acc.s2[slot] = fma(cd * Y, Y, acc.s2[slot]);
+            if (FIXED) {
+                acc.i1[slot] += static_cast<int64_t>(c) * Yint;
+                const uint64_t a = static_cast<uint64_t>(Yint < 0 ? -Yint : Yint);
+                const uint64_t sq = a * a;
+#if defined(__HIP_DEVICE_COMPILE__)
+                const uint64_t hi = __umul64hi(sq, uint64_t(c));
+#else
+                const uint64_t hi = static_cast<uint64_t>((static_cast<unsigned __int128>(sq) * c) >> 64);
+#endif
+                const uint64_t lo = sq * uint64_t(c);
+                const uint64_t nlo = acc.i2lo[slot] + lo;
+                acc.i2hi[slot] += hi + (nlo < lo ? 1u : 0u);
+                acc.i2lo[slot] = nlo;
+            }
+        }
+        acc.n += c;
+        if (FIXED) acc.sat += c * ax.nsat;
+    }
+
     __host__ __device__ __forceinline__ static void finish(const LevelDev& L, const WorkDev& W,
                                                            uint64_t pidx, const FSide<ExactT>& ex,
                                                            const FSide<float>& ap, XSide& ax,
@@ -353,29 +527,9 @@ struct PathBody {
         for (int slot = 0; slot < NP; ++slot) {
             const int p = NP == 1 ? L.payoff_single : slot;
             if (NP != 1 && !((L.payoff_mask >> p) & 1u)) continue;
-            double Ye = 0.0, Ya = 0.0, Y;
-            int64_t Yint = 0;
-            if (HAS_EXACT) {
-                const ExactT pf = ex.payoff(p, true, lev, ek, eb);
-                const ExactT pc = lev ? ex.payoff(p, false, lev - 1, ek, eb) : ExactT(0);
-                Ye = static_cast<double>(pf - pc);
-            }
-            if (HAS_TABLE) {
-                if (FIXED) {
-                    const int64_t pf = ax.payoff(p, true, lev, L);
-                    const int64_t pc = lev ? ax.payoff(p, false, lev - 1, L) : 0;
-                    Yint = pf - pc;
-                    Ya = ldexp(static_cast<double>(Yint), -L.fX);
-                } else {
-                    const float pf = ap.payoff(p, true, lev, L.fk, L.fb);
-                    const float pc = lev ? ap.payoff(p, false, lev - 1, L.fk, L.fb) : 0.0f;
-                    const float y = pf - pc;
-                    Ya = static_cast<double>(y);
-                }
-            }
-            if (EST == MLMC_EST_PLAIN) Y = Ye;
-            else if (EST == MLMC_EST_APPROX) Y = Ya;
-            else Y = Ye - Ya;
+            double Ye, Ya, Y;
+            int64_t Yint;
+            sample(L, p, ex, ap, ax, ek, eb, Ye, Ya, Yint, Y);
             if (!__builtin_isfinite(Y)) { acc.nonfinite += 1; Y = 0.0; }
             acc.s1[slot] += Y;
             acc.s2[slot] = fma(Y, Y, acc.s2[slot]);

@@ -16,6 +16,7 @@ struct HostGroups {
     const LevelDev* L;
     const WorkDev* W;
     const void* tab;
+    bool buffered;                 // exact normals computed ahead (the runtime's default rule)
     SlotDev out{};
     template <class Tag>
     void operator()(Tag) {
@@ -26,7 +27,37 @@ struct HostGroups {
         const uint64_t g0 = W->path_begin / G, g1 = (W->path_end - 1) / G + 1;
         Acc<Tag::np> acc;
         acc_zero(acc);
-        for (uint64_t g = g0; g < g1; ++g) B::run_group(*L, *W, g, tab, acc);
+        if (B::HIST && L->level == 0) {
+            std::vector<uint32_t> hist(L->table_entries, 0u);
+            auto count = [&](uint32_t k) { hist[k] += 1u; };
+            for (uint64_t g = g0; g < g1; ++g) B::hist_group(*L, *W, g, tab, count);
+            for (uint32_t k = 0; k < L->table_entries; ++k)
+                if (hist[k]) B::hist_accumulate(*L, tab, k, hist[k], acc);
+        } else if (B::HAS_EXACT && buffered) {
+            // the buffered exact path: words and normals ahead, step-major, as k_normals
+            using ZT = typename B::ExactT;
+            const uint64_t P = W->path_end - W->path_begin, NN = uint64_t(1) << L->level;
+            std::vector<uint32_t> Jb(P * NN);
+            std::vector<ZT> Zb(P * NN);
+            for (uint64_t b = (W->path_begin << L->level) / 4; b < (W->path_end << L->level) / 4; ++b) {
+                const u32x4 r = philox4x32_10(u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32),
+                                                    W->c2, W->c3}, W->k0, W->k1);
+                const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+                for (int w = 0; w < 4; ++w) {
+                    const uint64_t g = 4 * b + w;
+                    const uint64_t idx = (g & (NN - 1)) * P + ((g >> L->level) - W->path_begin);
+                    Jb[idx] = wd[w];
+                    Zb[idx] = sizeof(ZT) == 4 ? static_cast<ZT>(norminv_f32(wd[w]))
+                                              : static_cast<ZT>(norminv_f64(wd[w]));
+                }
+            }
+            WorkDev W2 = *W;
+            W2.jbuf = reinterpret_cast<uint64_t>(Jb.data());
+            W2.zbuf = reinterpret_cast<uint64_t>(Zb.data());
+            for (uint64_t i = W->path_begin; i < W->path_end; ++i) B::run_path_buffered(*L, W2, i, tab, acc);
+        } else {
+            for (uint64_t g = g0; g < g1; ++g) B::run_group(*L, *W, g, tab, acc);
+        }
         std::memset(&out, 0, sizeof(out));
         for (int p = 0; p < Tag::np; ++p) {
             out.s1[p] = acc.s1[p];
@@ -67,7 +98,10 @@ extern "C" mlmc_status mlmc_check_paths_host(const mlmc_problem* prob, int32_t l
     W.path_begin = path_offset;
     W.path_end = path_offset + n_paths;
     W.debug = reinterpret_cast<uint64_t>(records);
-    HostGroups h{&lp.dev, &W, lp.table.empty() ? nullptr : lp.table.data()};
+    const Tuning tune;
+    const bool buffered = estimator != MLMC_EST_APPROX && level >= 2 && n_paths <= tune.zb_max_paths &&
+                          (n_paths << level) <= tune.zb_max_positions;
+    HostGroups h{&lp.dev, &W, lp.table.empty() ? nullptr : lp.table.data(), buffered};
     if (!dispatch_variant(lp.variant, h)) return MLMC_E_INVALID;
     const bool single = popcount32(prob->payoff_mask) == 1;
     int i = 0;

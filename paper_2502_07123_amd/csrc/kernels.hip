@@ -144,10 +144,64 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
         Acc<NP> acc;
         acc_zero(acc);
         const uint64_t gend = td.group_begin + td.n_groups;
-        for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
-            Body::run_group(L, W, g, s_tab, acc);
+        if (Body::HIST && L.level == 0) {
+            // level-0 approximate samples: count table indices in LDS, then add
+            // c_k copies of each index's sample (thread t takes k = t, t + B, ...)
+            uint32_t* hist = reinterpret_cast<uint32_t*>(s_tab + L.table_bytes);
+            for (uint32_t i = threadIdx.x; i < L.table_entries; i += blockDim.x) hist[i] = 0u;
+            __syncthreads();
+            auto count = [&](uint32_t k) { atomicAdd(&hist[k], 1u); };
+            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+                Body::hist_group(L, W, g, s_tab, count);
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < L.table_entries; k += blockDim.x) {
+                const uint32_t c = hist[k];
+                if (c) Body::hist_accumulate(L, s_tab, k, c, acc);
+            }
+        } else if (Body::HAS_EXACT && W.zbuf) {
+            // normals computed ahead: a group is one path
+            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+                Body::run_path_buffered(L, W, g, s_tab, acc);
+        } else {
+            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+                Body::run_group(L, W, g, s_tab, acc);
+        }
         block_store<NP, EST == MLMC_EST_CORR, ARITH == MLMC_ARITH_FIXED && EST == MLMC_EST_APPROX>(
             acc, &slots[td.slot], red);
+    }
+}
+
+// Exact normals ahead of the path kernel for works with few, long paths: tiles
+// are ranges of Philox blocks b of the work's stream (positions 4b .. 4b + 3);
+// each thread computes one block's four words and their exact normals and stores
+// them step-major (index n P + path offset) so the path kernel reads coalesced.
+template <bool F32>
+__global__ void __launch_bounds__(256)
+k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __restrict__ works,
+          const LevelDev* __restrict__ levels) {
+    using ZT = typename std::conditional<F32, float, double>::type;
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const TileDev td = tiles[t];
+        const WorkDev W = works[td.work];
+        const int lev = levels[W.lvl].level;
+        const uint64_t P = W.path_end - W.path_begin;
+        ZT* Zb = reinterpret_cast<ZT*>(W.zbuf);
+        uint32_t* Jb = reinterpret_cast<uint32_t*>(W.jbuf);
+        const uint64_t bend = td.group_begin + td.n_groups;
+        for (uint64_t b = td.group_begin + threadIdx.x; b < bend; b += blockDim.x) {
+            const u32x4 r = philox4x32_10(
+                u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), W.c2, W.c3}, W.k0, W.k1);
+            const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll 1
+            for (int w = 0; w < 4; ++w) {
+                const uint64_t g = 4 * b + w;
+                const uint64_t i = g >> lev, n = g & ((uint64_t(1) << lev) - 1);
+                const uint64_t idx = n * P + (i - W.path_begin);
+                Jb[idx] = wd[w];
+                if (F32) Zb[idx] = static_cast<ZT>(norminv_f32(wd[w]));
+                else Zb[idx] = static_cast<ZT>(norminv_f64(wd[w]));
+            }
+        }
     }
 }
 
@@ -283,6 +337,14 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
     const PathKernel k = reinterpret_cast<PathKernel>(vi.fn);
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds_bytes, st, tiles, n_tiles, works, levels,
                        tables, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev* tiles,
+                          uint32_t n_tiles, const WorkDev* works, const LevelDev* levels) {
+    if (n_tiles == 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_normals<true>, dim3(grid), dim3(256), 0, st, tiles, n_tiles, works, levels);
+    else hipLaunchKernelGGL(k_normals<false>, dim3(grid), dim3(256), 0, st, tiles, n_tiles, works, levels);
     return hipGetLastError();
 }
 

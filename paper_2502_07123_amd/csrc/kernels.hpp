@@ -83,6 +83,10 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
                         SlotDev* slots);
 
+// exact normals ahead of the path kernel (FP32 for the plain-FP32 estimator, else FP64)
+hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev* tiles,
+                          uint32_t n_tiles, const WorkDev* works, const LevelDev* levels);
+
 // sums[rd.sums] (+)= ordered sum of the work's tile slots; compact[w] = the result
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
                          SlotDev* sums, SlotDev* compact);

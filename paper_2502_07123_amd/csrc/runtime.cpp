@@ -142,6 +142,10 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
     }
     std::vector<TileDev> tiles;
     std::vector<ReduceDev> reds(works.size());
+    // works with few, long paths get their exact normals computed ahead (k_normals)
+    std::vector<TileDev> ntiles[2];                 // [0]: FP64 normals, [1]: FP32
+    std::vector<size_t> zb_bytes(works.size(), 0), zb_off(works.size(), 0);
+    std::vector<int> zb_f32(works.size(), -1);
     for (auto& kv : groups) {
         LaunchGroup& g = kv.second;
         g.vi = variant_info(g.v);
@@ -153,7 +157,26 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
         for (uint32_t wi : g.works) {
             const WorkSpec& w = works[wi];
             const uint64_t N = uint64_t(1) << w.level;
-            const uint64_t S = group_span(w.level, static_cast<uint32_t>(g.vi.wpb));
+            const bool zb = w.est != MLMC_EST_APPROX && w.level >= 2 && w.n <= ctx->tune.zb_max_paths &&
+                            (w.n << w.level) <= ctx->tune.zb_max_positions;
+            if (zb) {
+                const bool f32 = w.est == MLMC_EST_PLAIN && w.prec->arith == MLMC_ARITH_FP32;
+                zb_f32[wi] = f32 ? 1 : 0;
+                const uint64_t pos = w.n << w.level;
+                zb_bytes[wi] = align_up(pos * 4, 256) + align_up(pos * (f32 ? 4 : 8), 256);
+                const uint64_t b0 = (w.path_begin << w.level) / 4, b1 = ((w.path_begin + w.n) << w.level) / 4;
+                for (uint64_t b = b0; b < b1; b += 1024) {
+                    TileDev t;
+                    t.work = wi;
+                    t.slot = 0;
+                    t.group_begin = b;
+                    t.n_groups = static_cast<uint32_t>(std::min<uint64_t>(1024, b1 - b));
+                    t.pad = 0;
+                    ntiles[f32 ? 1 : 0].push_back(t);
+                }
+            }
+            // a buffered work's group is one path
+            const uint64_t S = zb ? N : group_span(w.level, static_cast<uint32_t>(g.vi.wpb));
             const uint64_t G = S >> w.level;                       // paths per group
             const uint64_t g0 = w.path_begin / G;
             const uint64_t g1 = (w.path_begin + w.n - 1) / G + 1;
@@ -181,13 +204,17 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
             reds[wi].slot_end = static_cast<uint32_t>(tiles.size());
             reds[wi].sums = w.sums;
             reds[wi].accumulate = w.accumulate ? 1u : 0u;
-            g.lds = std::max<uint32_t>(g.lds, levels[wdev[wi].lvl].table_bytes);
+            // table, plus the level-0 index histogram of the approximate estimator
+            const LevelDev& Lw = levels[wdev[wi].lvl];
+            g.lds = std::max<uint32_t>(
+                g.lds, Lw.table_bytes + (g.v.est == MLMC_EST_APPROX ? 4u * Lw.table_entries : 0u));
         }
         g.t1 = static_cast<uint32_t>(tiles.size());
     }
     if (tiles.size() >= (size_t(1) << 31)) return fail(ctx, MLMC_E_NOMEM, "too many tiles");
 
-    // 3. workspace layout: [sums | compact | levels | works | tables | tiles | reds | slots]
+    // 3. workspace layout:
+    //    [sums | compact | levels | works | tables | tiles | reds | normal tiles | slots | normals]
     const size_t o_sums = 0;
     const size_t o_comp = align_up(o_sums + size_t(n_sums) * sizeof(SlotDev), 256);
     const size_t o_lvl = align_up(o_comp + works.size() * sizeof(SlotDev), 256);
@@ -195,8 +222,19 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
     const size_t o_tab = align_up(o_work + wdev.size() * sizeof(WorkDev), 256);
     const size_t o_tile = align_up(o_tab + tables.size(), 256);
     const size_t o_red = align_up(o_tile + tiles.size() * sizeof(TileDev), 256);
-    const size_t o_slot = align_up(o_red + reds.size() * sizeof(ReduceDev), 256);
-    const size_t total = o_slot + tiles.size() * sizeof(SlotDev);
+    const size_t o_nt0 = align_up(o_red + reds.size() * sizeof(ReduceDev), 256);
+    const size_t o_nt1 = align_up(o_nt0 + ntiles[0].size() * sizeof(TileDev), 256);
+    const size_t o_slot = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
+    size_t o_zb = align_up(o_slot + tiles.size() * sizeof(SlotDev), 256);
+    for (size_t i = 0; i < works.size(); ++i) {
+        if (zb_f32[i] < 0) continue;
+        zb_off[i] = o_zb;
+        const uint64_t pos = works[i].n << works[i].level;
+        wdev[i].jbuf = reinterpret_cast<uint64_t>(ctx->ws + o_zb);
+        wdev[i].zbuf = reinterpret_cast<uint64_t>(ctx->ws + o_zb + align_up(pos * 4, 256));
+        o_zb += zb_bytes[i];
+    }
+    const size_t total = o_zb;
     if (total > ctx->ws_bytes)
         return fail(ctx, MLMC_E_NOMEM, "workspace too small: need " + std::to_string(total) + " bytes");
     const size_t up_bytes = o_slot - o_lvl;
@@ -212,9 +250,21 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
     if (!tables.empty()) std::memcpy(h + (o_tab - o_lvl), tables.data(), tables.size());
     std::memcpy(h + (o_tile - o_lvl), tiles.data(), tiles.size() * sizeof(TileDev));
     std::memcpy(h + (o_red - o_lvl), reds.data(), reds.size() * sizeof(ReduceDev));
+    if (!ntiles[0].empty()) std::memcpy(h + (o_nt0 - o_lvl), ntiles[0].data(), ntiles[0].size() * sizeof(TileDev));
+    if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
     uint8_t* d = ctx->ws;
     hipStream_t s = ctx->stream;
     HIPCHK(hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s));
+    // exact normals ahead of the path kernels for the buffered works
+    const uint32_t ngrid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * 4;
+    for (int f = 0; f < 2; ++f) {
+        const uint32_t nn = static_cast<uint32_t>(ntiles[f].size());
+        if (!nn) continue;
+        HIPCHK(launch_normals(f == 1, std::min(nn, ngrid), s,
+                              reinterpret_cast<const TileDev*>(d + (f ? o_nt1 : o_nt0)), nn,
+                              reinterpret_cast<const WorkDev*>(d + o_work),
+                              reinterpret_cast<const LevelDev*>(d + o_lvl)));
+    }
 
     // 4. path kernels, one per variant, then the fixed-order reduction
     const uint32_t max_grid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * ctx->tune.blocks_per_cu;
@@ -634,6 +684,37 @@ mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_leve
         for (int p = 0; p < MLMC_NPAYOFF; ++p)
             if ((mask >> p) & 1u) slot_to_sums(res[i], single ? 0 : p, works[i].out[j++]);
     }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out) {
+    if (!ctx || !out) return MLMC_E_INVALID;
+    out->struct_size = sizeof(mlmc_tuning);
+    out->block_table = ctx->tune.block_table;
+    out->block_exact = ctx->tune.block_exact;
+    out->tile_steps = ctx->tune.tile_steps;
+    out->blocks_per_cu = ctx->tune.blocks_per_cu;
+    out->min_tiles = ctx->tune.min_tiles;
+    out->zb_max_paths = ctx->tune.zb_max_paths;
+    out->zb_max_positions = ctx->tune.zb_max_positions;
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_set_tuning(mlmc_context* ctx, const mlmc_tuning* t) {
+    if (!ctx || !t) return MLMC_E_INVALID;
+    if (t->struct_size != sizeof(mlmc_tuning)) return fail(ctx, MLMC_E_VERSION, "mlmc_tuning.struct_size mismatch");
+    auto pow2ish = [](uint32_t b, uint32_t hi) { return b >= 64 && b <= hi && b % 64 == 0; };
+    if (!pow2ish(t->block_table, 1024) || !pow2ish(t->block_exact, 256) || t->tile_steps < 1 ||
+        t->blocks_per_cu < 1 || t->blocks_per_cu > 64 || t->min_tiles < 1)
+        return fail(ctx, MLMC_E_INVALID, "tuning out of range");
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    ctx->tune.block_table = t->block_table;
+    ctx->tune.block_exact = t->block_exact;
+    ctx->tune.tile_steps = t->tile_steps;
+    ctx->tune.blocks_per_cu = t->blocks_per_cu;
+    ctx->tune.min_tiles = t->min_tiles;
+    ctx->tune.zb_max_paths = t->zb_max_paths;
+    ctx->tune.zb_max_positions = t->zb_max_positions;
     return MLMC_OK;
 }
 

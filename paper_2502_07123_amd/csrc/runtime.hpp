@@ -29,6 +29,10 @@ struct Tuning {
     uint32_t tile_steps = 1u << 16; // path-steps per tile (target)
     uint32_t blocks_per_cu = 8;     // persistent grid = CUs * blocks_per_cu (cap)
     uint32_t min_tiles = 2048;      // a work is split into at least this many tiles when it can be
+    // exact-normal works with at most zb_max_paths paths (and zb_max_positions
+    // stream positions) get their normals computed ahead, off the paths' chains
+    uint64_t zb_max_paths = 1u << 15;
+    uint64_t zb_max_positions = 1u << 22;
 };
 
 // One (option, level, estimator) path range of a launch.

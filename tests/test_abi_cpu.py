@@ -40,7 +40,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 STRUCTS = {"mlmc_problem": _lib.Problem, "mlmc_precision": _lib.Precision, "mlmc_sums": _lib.Sums,
            "mlmc_level_work": _lib.LevelWork, "mlmc_kernel_stat": _lib.KernelStat,
            "mlmc_run_config": _lib.RunConfig, "mlmc_level_stats": _lib.LevelStats,
-           "mlmc_result": _lib.Result, "mlmc_server_config": _lib.ServerConfig,
+           "mlmc_result": _lib.Result, "mlmc_server_config": _lib.ServerConfig, "mlmc_tuning": _lib.Tuning,
            "mlmc_request": _lib.Request}
 
 

@@ -35,14 +35,40 @@ def test_paths_and_sums(ctx, case, level, payoffs):
     check_records(case, level, n, off, payoffs, sums, rec, o)
 
 
+EXACT_CASES = [c for c in CASES if c[1] != M.EST_APPROX]
+
+
+@pytest.mark.parametrize("level", [2, 5])
+@pytest.mark.parametrize("case", EXACT_CASES, ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("ahead", [True, False], ids=["normals-ahead", "normals-inline"])
+def test_exact_normals_ahead_and_inline(ctx, case, level, ahead):
+    """Exact-normal works with few paths get their normals from the pre-pass kernel;
+    with the pre-pass disabled the path kernel computes them: both match the oracle."""
+    scheme, est, arith, packed = case
+    saved = ctx.get_tuning()
+    ctx.set_tuning(zb_max_paths=(1 << 15) if ahead else 0)
+    try:
+        n, off = 3001, 77
+        prob = M.make_problem(scheme, PAYS, **GBM)
+        prec = M.make_precision(arith, case_q(case), packed, WIDE_FMT)
+        sums, rec = ctx.level_sums(prob, level, n, off, prec, est, SEED, debug=True)
+        o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS)
+        check_records(case, level, n, off, PAYS, sums, rec, o)
+    finally:
+        ctx.set_tuning(**saved)
+
+
 def test_sums_without_debug_equal_debug_run(ctx):
-    """The debug buffer is a flag of the same kernel: identical sums either way."""
+    """The debug buffer is a flag of the same kernel: identical sums either way
+    (per-path code, level-0 index histogram, normals computed ahead)."""
     prob = M.make_problem("milstein", PAYS, **GBM)
     prec = M.make_precision("fp32", 8)
-    for est in (M.EST_PLAIN, M.EST_APPROX, M.EST_CORR):
-        a = ctx.level_sums(prob, 5, 50_000, 3, prec, est, SEED)
-        b, _ = ctx.level_sums(prob, 5, 50_000, 3, prec, est, SEED, debug=True)
-        assert a == b
+    for est, level, n in ((M.EST_PLAIN, 5, 50_000), (M.EST_APPROX, 5, 50_000),
+                          (M.EST_CORR, 5, 50_000), (M.EST_APPROX, 0, 300_000),
+                          (M.EST_CORR, 6, 5_000), (M.EST_PLAIN, 3, 7_000)):
+        a = ctx.level_sums(prob, level, n, 3, prec, est, SEED)
+        b, _ = ctx.level_sums(prob, level, n, 3, prec, est, SEED, debug=True)
+        assert a == b, (est, level)
 
 
 def test_repeatable_and_offset_split(ctx):
