@@ -7,7 +7,8 @@ four per 32-bit word) in FP32, the correction estimator FP64 minus FP32 on the s
 uniforms; N_l (approximate) and M_l (correction) come from the nested optimal
 allocation at eps = 1e-3 in price units (variance eps^2, theta = 1) after an
 untimed pilot.  One step = all 18 (level, estimator) level sums in one launch
-sequence plus the host combination into the price estimate.
+sequence plus the host combination into the price estimate; consecutive steps are
+pipelined (the host marshals and enqueues step k + 1 while step k runs).
 
 Printed: one JSON line (metric path-steps/s), with the VALU roofline of the
 dominant kernel (HIP-event timing inside the timed region), the CPU oracle timed on
@@ -70,16 +71,14 @@ def make_items(M, prob, prec_a, prec_c, Na, Nc, offset):
     return items
 
 
-def combine(res, scale):
-    est, var = 0.0, 0.0
-    for r in res:
-        s = r["euro"]
-        n = s["n"]
-        m = s["sum1"] / n
-        v = max((s["sum2"] - s["sum1"] ** 2 / n) / (n - 1), 0.0)
-        est += m
-        var += v / n
-    return scale * est, scale * math.sqrt(var)
+def combine_np(S, scale):
+    """Price estimate and its standard error from a batch's sums (R9 variances)."""
+    import numpy as np
+    s = S[:, 0]
+    n = s["n"].astype(np.float64)
+    m = s["sum1"] / n
+    v = np.maximum((s["sum2"] - s["sum1"] ** 2 / n) / (n - 1.0), 0.0)
+    return scale * float(m.sum()), scale * math.sqrt(float((v / n).sum()))
 
 
 def cpu_baseline(Na, Nc, budget_paths_steps=2.0e7):
@@ -155,18 +154,35 @@ def main():
     Na, Nc = N[:LEVELS], N[LEVELS:]
     path_steps = int(sum(int(Na[l]) << l for l in range(LEVELS)) + sum(int(Nc[l]) << l for l in range(LEVELS)))
 
+    # two marshalled batches alternate so that the host prepares step k + 1 while the
+    # GPU runs step k; each step draws fresh paths (path offsets advance)
+    batches = [ctx.sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, 0)) for _ in range(2)]
     off = N_PILOT
-    for w in range(args.warmup):
-        ctx.level_sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, off))
-        off += int(max(N))
+    ests = []
+
+    def run_steps(k_steps, record):
+        nonlocal off
+        for k in range(k_steps):
+            b = batches[k % 2]
+            if b._pending is not None:
+                b.wait()
+                if record:
+                    ests.append(combine_np(b.sums, scale))
+            b.offsets[:] = off
+            off += int(max(N))
+            b.enqueue()
+        for k in range(k_steps, k_steps + 2):
+            b = batches[k % 2]
+            if b._pending is not None:
+                b.wait()
+                if record:
+                    ests.append(combine_np(b.sums, scale))
+
+    run_steps(args.warmup, False)
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ests = []
-    for k in range(args.steps):
-        res = ctx.level_sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, off))
-        ests.append(combine(res, scale))
-        off += int(max(N))
+    run_steps(args.steps, True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = ctx.kernel_stats()

@@ -186,7 +186,8 @@ mlmc_status mlmc_level_sums(mlmc_context* ctx, const mlmc_problem* prob, int32_t
                             uint32_t option_id, mlmc_sums* out, void* debug_paths);
 
 /* Many level sums in one launch sequence (one persistent kernel per estimator /
- * arithmetic class over a ragged list of tiles, then one fixed-order reduction):
+ * arithmetic class over a ragged list of tiles; the block finishing a work's last
+ * tile adds the work's tile sums in a fixed order):
  * e.g. every (level, estimator) of a nested MLMC estimate with its own N_l
  * (Section 2.2).  Each work's sums equal those of mlmc_level_sums on the same
  * arguments.  works: host array; each out points at popcount(payoff_mask) sums.
@@ -203,6 +204,22 @@ typedef struct mlmc_level_work {
 } mlmc_level_work;
 
 mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works);
+
+/* The same batch without waiting: validates, plans, uploads and launches it on the
+ * context's stream and returns a ticket (> 0).  Batches run in enqueue order; up to
+ * four are in flight, each in its own part of the workspace (an enqueue that finds
+ * no room waits for the oldest).  The prob/prec structs may be reused at once; each
+ * work's out array must stay valid until mlmc_level_sums_wait on the ticket (or on a
+ * later one) returns, and is written then, or by any later call on the context that
+ * has to wait for the batch.  Results equal mlmc_level_sums_batch's.  Errors as
+ * mlmc_level_sums_batch, from the enqueue (nothing was launched) or from the wait. */
+mlmc_status mlmc_level_sums_enqueue(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works,
+                                    uint64_t* ticket);
+
+/* Waits for an enqueued batch and returns its status (its outs are written).  Every
+ * ticket is waited on once; MLMC_E_UNKNOWN_TICKET for a ticket never issued or
+ * already waited on. */
+mlmc_status mlmc_level_sums_wait(mlmc_context* ctx, uint64_t ticket);
 
 /* Kernel timing.  With timing on, every path-kernel launch is bracketed by HIP
  * events on the context's stream; per kernel class the library accumulates the

@@ -11,13 +11,14 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, PAYOFFS, RECORD_DTYPE, VARS, KernelStat, LevelWork, Tuning,
-                   MlmcError, Problem, Precision, Request, Result, RunConfig, ServerConfig, Sums,
-                   check, lib, make_precision, make_problem, make_run_config)
+from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, LEVELWORK_DTYPE, PAYOFFS, RECORD_DTYPE, SUMS_DTYPE,
+                   VARS, KernelStat, LevelWork, Tuning, MlmcError, Problem, Precision, Request, Result,
+                   RunConfig, ServerConfig, Sums, check, lib, make_precision, make_problem, make_run_config)
 
 __all__ = ["Context", "make_problem", "make_precision", "make_run_config", "build_table",
            "stream_words", "check_paths_host", "allocate", "validate", "MlmcError",
-           "EST_PLAIN", "EST_APPROX", "EST_CORR", "PAYOFFS", "VARS", "RECORD_DTYPE"]
+           "EST_PLAIN", "EST_APPROX", "EST_CORR", "PAYOFFS", "VARS", "RECORD_DTYPE", "SUMS_DTYPE",
+           "SumsBatch"]
 
 
 def _payoff_names(problem):
@@ -96,6 +97,10 @@ class Context:
         check(lib().mlmc_level_sums_batch(self.h, n, works), self.h)
         return [{nm: out[j].as_dict() for j, nm in enumerate(names)} for names, out in outs]
 
+    def sums_batch(self, items):
+        """A reusable batch of level-sum works (see SumsBatch)."""
+        return SumsBatch(self, items)
+
     def get_tuning(self):
         t = Tuning()
         check(lib().mlmc_get_tuning(self.h, C.byref(t)), self.h)
@@ -155,6 +160,71 @@ class Context:
 
     def server_stop(self):
         check(lib().mlmc_server_stop(self.h), self.h)
+
+
+class SumsBatch:
+    """A fixed list of works, items as for Context.level_sums_batch, marshalled once.
+    `offsets` (numpy view, one per work) and `seeds` may be changed between runs;
+    after run() or wait(), `sums` is a numpy array of SUMS_DTYPE per work and payoff
+    (shape (n_works, max payoffs per work), payoffs in increasing order).
+
+    enqueue() launches the batch and returns a ticket without waiting; wait(ticket)
+    waits for it.  The sums buffer is written when the batch lands, so a second
+    enqueue of the same SumsBatch must follow the wait of the first (use two batches
+    to keep two in flight)."""
+
+    def __init__(self, ctx, items):
+        self.ctx = ctx
+        n = len(items)
+        self.n = n
+        self._keep = []
+        self.payoffs = []
+        npay = max(bin(it[0].payoff_mask).count("1") for it in items)
+        self._out = (Sums * (n * npay))()
+        self.sums = np.frombuffer(self._out, dtype=SUMS_DTYPE).reshape(n, npay)
+        self._works = (LevelWork * n)()
+        w = np.frombuffer(self._works, dtype=LEVELWORK_DTYPE)
+        base = C.addressof(self._out)
+        for i, (prob, level, npaths, off, prec, est, seed, opt) in enumerate(items):
+            self._keep.append((prob, prec))
+            self.payoffs.append(_payoff_names(prob))
+            w[i] = (C.sizeof(LevelWork), level, est, opt, int(npaths), int(off), int(seed),
+                    C.addressof(prob), C.addressof(prec), base + i * npay * C.sizeof(Sums))
+        self.offsets = w["path_offset"]
+        self.seeds = w["seed"]
+        self.n_paths = w["n_paths"]
+        self._pending = None
+
+    def run(self):
+        check(lib().mlmc_level_sums_batch(self.ctx.h, self.n, self._works), self.ctx.h)
+        return self.sums
+
+    def enqueue(self):
+        if self._pending is not None:
+            raise RuntimeError("this batch is still in flight: wait for it first")
+        t = C.c_uint64()
+        check(lib().mlmc_level_sums_enqueue(self.ctx.h, self.n, self._works, C.byref(t)), self.ctx.h)
+        self._pending = t.value
+        return t.value
+
+    def wait(self, ticket=None):
+        t = self._pending if ticket is None else ticket
+        self._pending = None
+        check(lib().mlmc_level_sums_wait(self.ctx.h, int(t)), self.ctx.h)
+        return self.sums
+
+    def as_dicts(self):
+        """One {payoff: sums dict} per work (as Context.level_sums_batch)."""
+        out = []
+        for i, names in enumerate(self.payoffs):
+            d = {}
+            for j, nm in enumerate(names):
+                r = self.sums[i, j]
+                x = {f: r[f].item() for f in SUMS_DTYPE.names}
+                x["isum2"] = (int(r["isum2_hi"]) << 64) | int(r["isum2_lo"])
+                d[nm] = x
+            out.append(d)
+        return out
 
 
 # ---------------------------------------------------------- host-side helpers

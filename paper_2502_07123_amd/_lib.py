@@ -58,6 +58,14 @@ class Sums(C.Structure):
         return d
 
 
+# numpy views of the same layouts (checked against the ctypes structs in the tests)
+SUMS_DTYPE = np.dtype([("n", "<u8"), ("sum1", "<f8"), ("sum2", "<f8"), ("isum1", "<i8"),
+                       ("isum2_lo", "<u8"), ("isum2_hi", "<u8"), ("esum1", "<f8"), ("esum2", "<f8"),
+                       ("saturations", "<u8"), ("nonfinite", "<u8")])
+LEVELWORK_DTYPE = np.dtype([("struct_size", "<u4"), ("level", "<i4"), ("estimator", "<i4"),
+                            ("option_id", "<u4"), ("n_paths", "<u8"), ("path_offset", "<u8"),
+                            ("seed", "<u8"), ("prob", "<u8"), ("prec", "<u8"), ("out", "<u8")])
+
 RECORD_DTYPE = np.dtype([("Y", "<f8", (NPAYOFF,)), ("Yraw", "<i8", (NPAYOFF,)),
                          ("XN_exact", "<f8"), ("XcN_exact", "<f8"), ("XN_approx", "<f8"),
                          ("XcN_approx", "<f8"), ("XN_raw", "<i8"), ("XcN_raw", "<i8"),
@@ -149,6 +157,8 @@ def lib():
         "mlmc_level_sums": (st, [vp, P(Problem), i32, u64, u64, P(Precision), i32, u64, u32,
                                  P(Sums), vp]),
         "mlmc_level_sums_batch": (st, [vp, u32, P(LevelWork)]),
+        "mlmc_level_sums_enqueue": (st, [vp, u32, P(LevelWork), P(u64)]),
+        "mlmc_level_sums_wait": (st, [vp, u64]),
         "mlmc_set_timing": (st, [vp, i32]),
         "mlmc_get_tuning": (st, [vp, P(Tuning)]),
         "mlmc_set_tuning": (st, [vp, P(Tuning)]),
@@ -176,7 +186,8 @@ def lib():
 
 
 EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_context_create",
-            "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_batch", "mlmc_set_timing",
+            "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_batch",
+            "mlmc_level_sums_enqueue", "mlmc_level_sums_wait", "mlmc_set_timing",
             "mlmc_get_tuning", "mlmc_set_tuning",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_server_stop",

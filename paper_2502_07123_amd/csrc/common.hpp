@@ -17,6 +17,20 @@ namespace mlmc {
 
 constexpr int NPAY = MLMC_NPAYOFF;
 
+// Device buffers whose addresses travel inside structs are global memory; naming
+// the address space lets the compiler use global (not flat) loads and stores, which
+// do not count against the LDS wait counter, so an LDS access does not have to wait
+// for outstanding global loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MLMC_GLOBAL __attribute__((address_space(1)))
+#else
+#define MLMC_GLOBAL
+#endif
+template <typename T>
+__host__ __device__ __forceinline__ MLMC_GLOBAL T* global_ptr(uint64_t addr) {
+    return reinterpret_cast<MLMC_GLOBAL T*>(addr);
+}
+
 // Stream positions of one path group: lcm(2^level, wpb), so that a group holds
 // whole paths and whole Philox blocks (wpb = 4 * indices per word).
 __host__ __device__ __forceinline__ uint64_t group_span(int level, uint32_t wpb) {
@@ -50,7 +64,7 @@ struct WorkDev {
     uint32_t lvl;             // index of its LevelDev
     uint32_t c2, c3;          // counter words: level | estimator << 8, option
     uint32_t k0, k1;          // key = seed
-    uint32_t sums;            // index of its accumulated sums
+    uint32_t pad0;
     uint64_t path_begin, path_end;
     uint64_t debug;           // device address of mlmc_path_record[path_end - path_begin] or 0
     // Normals computed ahead by k_normals (0: computed in the path kernel): for
@@ -77,8 +91,8 @@ struct SlotDev {
 
 struct ReduceDev {
     uint32_t slot_begin, slot_end;   // this work item's tile slots
-    uint32_t sums;                   // destination
-    uint32_t accumulate;             // add to the destination (1) or overwrite (0)
+    uint32_t kind;                   // sums present: 1 correction, 2 integer, 4 all payoffs
+    uint32_t pad;
 };
 
 }  // namespace mlmc

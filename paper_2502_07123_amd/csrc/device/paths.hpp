@@ -297,6 +297,17 @@ struct PathBody {
         }
     }
 
+    // Table index in field fi of a uniform word: q bits, fields from the most
+    // significant end (F == 1: the top q bits).
+    __host__ __device__ __forceinline__ static uint32_t index_field(uint32_t J, int fi, int q) {
+        if (F == 1) return J >> (32 - q);
+#if defined(__HIP_DEVICE_COMPILE__)
+        return __builtin_amdgcn_ubfe(J, static_cast<uint32_t>(32 - q * (fi + 1)), static_cast<uint32_t>(q));
+#else
+        return (J >> (32 - q * (fi + 1))) & ((1u << q) - 1u);
+#endif
+    }
+
     // Stream position sl of the group (odd = sl & 1, known at compile time when
     // unrolled since 4F is even); J the word holding it, fi its field.
     __host__ __device__ __forceinline__ static void step(
@@ -313,8 +324,7 @@ struct PathBody {
             if (HAS_TABLE) { if (FIXED) ax.init(L); else ap.init(); }
         }
         uint32_t k = 0;
-        if (HAS_TABLE)
-            k = (F == 1) ? (J >> (32 - q)) : ((J >> (32 - q * (fi + 1))) & ((1u << q) - 1u));
+        if (HAS_TABLE) k = index_field(J, fi, q);
         if (n == 0) { first_word = J; first_index = k; }
         if (HAS_EXACT) {
             if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J), L, coarse_on, odd, TRACK);
@@ -342,6 +352,44 @@ struct PathBody {
     // One path of a work whose words and exact normals were computed ahead by
     // k_normals (works with few, long paths: the inverse normal then leaves the
     // path's sequential chain).  Same steps and records as run_group.
+    // Steps 0 .. N-1 of one buffered path, AH (<= N, dividing N) loads in flight.
+    // Loads are unconditional (the index is clamped to the last step) so that no
+    // branch join forces an early wait on them.
+    template <uint32_t AH>
+    __host__ __device__ __forceinline__ static void buffered_steps(
+        const LevelDev& L, uint32_t N, uint64_t P, uint64_t col, const MLMC_GLOBAL uint32_t* Jb,
+        const MLMC_GLOBAL ExactT* Zb, const void* tab, FSide<ExactT>& ex, FSide<float>& ap, XSide& ax) {
+        const int q = L.q;
+        uint32_t jq[AH];
+        ExactT zq[AH];
+#pragma unroll
+        for (uint32_t h = 0; h < AH; ++h) {
+            jq[h] = Jb[uint64_t(h) * P + col];
+            zq[h] = Zb[uint64_t(h) * P + col];
+        }
+        for (uint32_t n = 0; n < N; n += AH) {
+#pragma unroll
+            for (uint32_t h = 0; h < AH; ++h) {
+                const uint32_t J = jq[h];
+                const ExactT Z = zq[h];
+                const uint32_t nn = n + AH + h < N ? n + AH + h : N - 1u;
+                jq[h] = Jb[uint64_t(nn) * P + col];
+                zq[h] = Zb[uint64_t(nn) * P + col];
+                exact_step<MIL>(ex, Z, L, true, (h & 1u) == 1u, TRACK);
+                if (HAS_TABLE) {
+                    const uint32_t k = J >> (32 - q);
+                    if (FIXED) {
+                        const int2 e = static_cast<const int2*>(tab)[k];
+                        fixed_step<MIL>(ax, e.x, e.y, L, true, (h & 1u) == 1u, TRACK);
+                    } else {
+                        const float2 e = static_cast<const float2*>(tab)[k];
+                        table_step<MIL>(ap, e.x, e.y, L, true, (h & 1u) == 1u, TRACK);
+                    }
+                }
+            }
+        }
+    }
+
     __host__ __device__ __forceinline__ static void run_path_buffered(const LevelDev& L,
                                                                       const WorkDev& W,
                                                                       uint64_t pidx, const void* tab,
@@ -350,8 +398,8 @@ struct PathBody {
         const uint32_t N = 1u << lev;
         const uint64_t P = W.path_end - W.path_begin;
         const uint64_t col = pidx - W.path_begin;
-        const ExactT* Zb = reinterpret_cast<const ExactT*>(W.zbuf);
-        const uint32_t* Jb = reinterpret_cast<const uint32_t*>(W.jbuf);
+        const MLMC_GLOBAL ExactT* Zb = global_ptr<const ExactT>(W.zbuf);
+        const MLMC_GLOBAL uint32_t* Jb = global_ptr<const uint32_t>(W.jbuf);
         const int q = L.q;
         FSide<ExactT> ex;
         FSide<float> ap;
@@ -360,25 +408,11 @@ struct PathBody {
         if (HAS_TABLE) { if (FIXED) ax.init(L); else ap.init(); }
         const uint32_t first_word = Jb[col];
         const uint32_t first_index = HAS_TABLE ? (first_word >> (32 - q)) : 0u;
-        // N >= 4 for buffered works: steps come in (even, odd) pairs
-        for (uint32_t n = 0; n < N; n += 2) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint64_t idx = uint64_t(n + h) * P + col;
-                const uint32_t J = Jb[idx];
-                exact_step<MIL>(ex, Zb[idx], L, true, h == 1, TRACK);
-                if (HAS_TABLE) {
-                    const uint32_t k = J >> (32 - q);
-                    if (FIXED) {
-                        const int2 e = static_cast<const int2*>(tab)[k];
-                        fixed_step<MIL>(ax, e.x, e.y, L, true, h == 1, TRACK);
-                    } else {
-                        const float2 e = static_cast<const float2*>(tab)[k];
-                        table_step<MIL>(ap, e.x, e.y, L, true, h == 1, TRACK);
-                    }
-                }
-            }
-        }
+        // The step loop is a serial chain: the word and normal of step n + AH are
+        // loaded while step n computes, so a global load's latency is paid once per AH
+        // steps.  N >= 4 is a power of two (steps come in (even, odd) pairs).
+        if (N >= 8) buffered_steps<8>(L, N, P, col, Jb, Zb, tab, ex, ap, ax);
+        else buffered_steps<4>(L, N, P, col, Jb, Zb, tab, ex, ap, ax);
         finish(L, W, pidx, ex, ap, ax, first_word, first_index, acc);
     }
 
@@ -451,13 +485,20 @@ struct PathBody {
         const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
         const bool full = path0 >= W.path_begin && path0 + WPB <= W.path_end;
         const int q = L.q;
+        if (full && !W.debug) {
+            // every path of the group is in range and no records: count only
+#pragma unroll
+            for (int wi = 0; wi < 4; ++wi)
+#pragma unroll
+                for (int fi = 0; fi < F; ++fi) count(index_field(wd[wi], fi, q));
+            return;
+        }
 #pragma unroll
         for (int wi = 0; wi < 4; ++wi) {
 #pragma unroll
             for (int fi = 0; fi < F; ++fi) {
                 const uint32_t J = wd[wi];
-                const uint32_t k =
-                    (F == 1) ? (J >> (32 - q)) : ((J >> (32 - q * (fi + 1))) & ((1u << q) - 1u));
+                const uint32_t k = index_field(J, fi, q);
                 const uint64_t pidx = path0 + uint64_t(wi * F + fi);
                 if (full || (pidx >= W.path_begin && pidx < W.path_end)) {
                     count(k);
@@ -519,8 +560,8 @@ struct PathBody {
                                                            uint32_t first_word,
                                                            uint32_t first_index, Acc<NP>& acc) {
         const int lev = L.level;
-        mlmc_path_record* rec =
-            W.debug ? reinterpret_cast<mlmc_path_record*>(W.debug) + (pidx - W.path_begin) : nullptr;
+        MLMC_GLOBAL mlmc_path_record* rec =
+            W.debug ? global_ptr<mlmc_path_record>(W.debug) + (pidx - W.path_begin) : nullptr;
         const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
         const ExactT eb = PLAIN32 ? ExactT(L.fb) : ExactT(L.b);
 #pragma unroll

@@ -6,10 +6,9 @@
 // thread runs path groups group_begin + tid, + blockDim, ... accumulating FP64 (and
 // exact integer) sums per payoff in registers, and the block reduces them in a
 // fixed order -- butterfly within each 64-lane wave, then waves in index order --
-// into the tile's own slot.  Results therefore do not depend on which block ran a
+// into the tile's own slot.  k_reduce then adds each work item's slots in a fixed
+// order into its result.  Results therefore do not depend on which block ran a
 // tile or on what else was in the launch.
-// k_reduce: one block per work item adds the item's tile slots in a fixed order
-// (optionally onto the running total).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -53,8 +52,11 @@ struct RedLds {
     uint64_t c[MAX_WAVES][3];
 };
 
+// Block sum of the per-thread accumulators (butterfly in each wave, then the waves
+// in index order) written by thread 0 to *out; the counts come as 64-bit values.
 template <int NP, bool CORR, bool INTS>
-__device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r) {
+__device__ __forceinline__ void block_store_counts(Acc<NP>& a, uint64_t cn, uint64_t csat, uint64_t cnf,
+                                                   SlotDev* out, RedLds& r) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
     double d[4 * NP];
@@ -69,9 +71,9 @@ __device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r)
             wave_sum128(a.i2lo[p], a.i2hi[p]);
         }
     }
-    const int64_t n = wave_sum(static_cast<int64_t>(a.n));
-    const int64_t sat = wave_sum(static_cast<int64_t>(a.sat));
-    const int64_t nf = wave_sum(static_cast<int64_t>(a.nonfinite));
+    const int64_t n = wave_sum(static_cast<int64_t>(cn));
+    const int64_t sat = wave_sum(static_cast<int64_t>(csat));
+    const int64_t nf = wave_sum(static_cast<int64_t>(cnf));
     __syncthreads();                           // previous tile's readers are done
     if (lane == 0) {
 #pragma unroll
@@ -115,10 +117,16 @@ __device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r)
     }
 }
 
-// Exact-normal kernels carry the FP64 inverse normal's constants: they get a
-// 256-thread bound (more registers per lane, no spills); table-only kernels 1024.
+template <int NP, bool CORR, bool INTS>
+__device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r) {
+    block_store_counts<NP, CORR, INTS>(a, a.n, a.sat, a.nonfinite, out, r);
+}
+
+// Exact-normal kernels carry the FP64 inverse normal's constants and fixed-point
+// kernels the wide integer sums: they get a 256-thread bound (more registers per
+// lane, no spills); FP32 table-only kernels 1024.
 template <int EST, int ARITH>
-constexpr int max_threads() { return EST == MLMC_EST_APPROX ? 1024 : 256; }
+constexpr int max_threads() { return EST == MLMC_EST_APPROX && ARITH != MLMC_ARITH_FIXED ? 1024 : 256; }
 
 template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, max_threads<EST, ARITH>())))
@@ -126,6 +134,8 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
         const LevelDev* __restrict__ levels, const uint8_t* __restrict__ tables,
         SlotDev* __restrict__ slots) {
     using Body = PathBody<EST, ARITH, MIL, NP, TRACK, F>;
+    constexpr bool CORR = EST == MLMC_EST_CORR;
+    constexpr bool INTS = ARITH == MLMC_ARITH_FIXED && EST == MLMC_EST_APPROX;
     extern __shared__ __align__(16) uint8_t s_tab[];
     __shared__ RedLds red;
     uint32_t cur = 0xFFFFFFFFu;
@@ -166,8 +176,7 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::run_group(L, W, g, s_tab, acc);
         }
-        block_store<NP, EST == MLMC_EST_CORR, ARITH == MLMC_ARITH_FIXED && EST == MLMC_EST_APPROX>(
-            acc, &slots[td.slot], red);
+        block_store<NP, CORR, INTS>(acc, &slots[td.slot], red);
     }
 }
 
@@ -185,8 +194,8 @@ k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __
         const WorkDev W = works[td.work];
         const int lev = levels[W.lvl].level;
         const uint64_t P = W.path_end - W.path_begin;
-        ZT* Zb = reinterpret_cast<ZT*>(W.zbuf);
-        uint32_t* Jb = reinterpret_cast<uint32_t*>(W.jbuf);
+        MLMC_GLOBAL ZT* Zb = global_ptr<ZT>(W.zbuf);
+        MLMC_GLOBAL uint32_t* Jb = global_ptr<uint32_t>(W.jbuf);
         const uint64_t bend = td.group_begin + td.n_groups;
         for (uint64_t b = td.group_begin + threadIdx.x; b < bend; b += blockDim.x) {
             const u32x4 r = philox4x32_10(
@@ -205,105 +214,61 @@ k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __
     }
 }
 
-// Sums of one work's tile slots in a fixed order: thread t adds slots t, t + B,
-// t + 2B, ... (B = 256), then a butterfly within each wave and the waves in index
-// order, onto the running total when accumulating.
-struct RedAcc {
-    double d[4 * NPAY];
-    int64_t i1[NPAY];
-    uint64_t lo[NPAY], hi[NPAY];
-    uint64_t c[3];
-};
+// Sums of one work item's tile slots in a fixed order that depends only on the
+// number of slots: lane v of wave w (8 waves) adds slots 64 c + v for chunks
+// c = w, w + 8, w + 16, ... in order; a butterfly adds each wave's lanes and the
+// waves are added in index order.  Only the payoffs, correction sums and integer
+// sums of the work's kernel variant are added; the rest of the result is zero.
+constexpr int REDUCE_THREADS = 512;
+constexpr int REDUCE_WAVES = REDUCE_THREADS / 64;
 
-__device__ __forceinline__ void red_zero(RedAcc& a) {
+template <int NP, bool CORR, bool INTS>
+__device__ __forceinline__ void reduce_work(const SlotDev* __restrict__ sl, uint32_t ns,
+                                            SlotDev* __restrict__ dst, RedLds& r) {
+    Acc<NP> a;
+    acc_zero(a);
+    uint64_t n = 0, sat = 0, nf = 0;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+#pragma unroll 4
+    for (uint32_t i = wave * 64u + lane; i < ns; i += REDUCE_THREADS) {
+        const SlotDev& x = sl[i];
 #pragma unroll
-    for (int i = 0; i < 4 * NPAY; ++i) a.d[i] = 0.0;
-#pragma unroll
-    for (int p = 0; p < NPAY; ++p) { a.i1[p] = 0; a.lo[p] = 0; a.hi[p] = 0; }
-    a.c[0] = a.c[1] = a.c[2] = 0;
-}
-
-__device__ __forceinline__ void add128(uint64_t& lo, uint64_t& hi, uint64_t blo, uint64_t bhi) {
-    const uint64_t nlo = lo + blo;
-    hi += bhi + (nlo < lo ? 1u : 0u);
-    lo = nlo;
-}
-
-__device__ __forceinline__ void red_add(RedAcc& a, const SlotDev& s) {
-#pragma unroll
-    for (int p = 0; p < NPAY; ++p) {
-        a.d[p] += s.s1[p];
-        a.d[NPAY + p] += s.s2[p];
-        a.d[2 * NPAY + p] += s.e1[p];
-        a.d[3 * NPAY + p] += s.e2[p];
-        a.i1[p] += s.i1[p];
-        add128(a.lo[p], a.hi[p], s.i2lo[p], s.i2hi[p]);
+        for (int p = 0; p < NP; ++p) {
+            a.s1[p] += x.s1[p];
+            a.s2[p] += x.s2[p];
+            if (CORR) {
+                a.e1[p] += x.e1[p];
+                a.e2[p] += x.e2[p];
+            }
+            if (INTS) {
+                a.i1[p] += x.i1[p];
+                const uint64_t lo = a.i2lo[p] + x.i2lo[p];
+                a.i2hi[p] += x.i2hi[p] + (lo < a.i2lo[p] ? 1u : 0u);
+                a.i2lo[p] = lo;
+            }
+        }
+        n += x.n;
+        sat += x.sat;
+        nf += x.nonfinite;
     }
-    a.c[0] += s.n;
-    a.c[1] += s.sat;
-    a.c[2] += s.nonfinite;
+    block_store_counts<NP, CORR, INTS>(a, n, sat, nf, dst, r);
 }
-
-__device__ __forceinline__ void red_add(RedAcc& a, const RedAcc& b) {
-#pragma unroll
-    for (int i = 0; i < 4 * NPAY; ++i) a.d[i] += b.d[i];
-#pragma unroll
-    for (int p = 0; p < NPAY; ++p) { a.i1[p] += b.i1[p]; add128(a.lo[p], a.hi[p], b.lo[p], b.hi[p]); }
-    a.c[0] += b.c[0];
-    a.c[1] += b.c[1];
-    a.c[2] += b.c[2];
-}
-
-__device__ __forceinline__ void red_wave(RedAcc& a) {
-#pragma unroll
-    for (int i = 0; i < 4 * NPAY; ++i) a.d[i] = wave_sum(a.d[i]);
-#pragma unroll
-    for (int p = 0; p < NPAY; ++p) {
-        a.i1[p] = wave_sum(a.i1[p]);
-        wave_sum128(a.lo[p], a.hi[p]);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) a.c[i] = static_cast<uint64_t>(wave_sum(static_cast<int64_t>(a.c[i])));
-}
-
-constexpr int REDUCE_THREADS = 256;
 
 __global__ void __launch_bounds__(REDUCE_THREADS)
-k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, uint32_t n,
-         SlotDev* __restrict__ sums, SlotDev* __restrict__ compact) {
-    __shared__ RedAcc part[REDUCE_THREADS / 64];
-    const uint32_t w = blockIdx.x;
-    if (w >= n) return;
-    const ReduceDev rd = rds[w];
-    SlotDev* dst = &sums[rd.sums];
-    RedAcc a;
-    red_zero(a);
-    for (uint32_t s = rd.slot_begin + threadIdx.x; s < rd.slot_end; s += blockDim.x) red_add(a, slots[s]);
-    red_wave(a);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) part[wave] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        RedAcc t;
-        red_zero(t);
-        if (rd.accumulate) red_add(t, *dst);
-        for (int v = 0; v < static_cast<int>(blockDim.x >> 6); ++v) red_add(t, part[v]);
-        SlotDev o;
-        for (int p = 0; p < NPAY; ++p) {
-            o.s1[p] = t.d[p];
-            o.s2[p] = t.d[NPAY + p];
-            o.e1[p] = t.d[2 * NPAY + p];
-            o.e2[p] = t.d[3 * NPAY + p];
-            o.i1[p] = t.i1[p];
-            o.i2lo[p] = t.lo[p];
-            o.i2hi[p] = t.hi[p];
-        }
-        o.n = t.c[0];
-        o.sat = t.c[1];
-        o.nonfinite = t.c[2];
-        o.pad = 0;
-        *dst = o;
-        compact[w] = o;
+k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, SlotDev* __restrict__ results) {
+    __shared__ RedLds red;
+    const ReduceDev rd = rds[blockIdx.x];
+    const SlotDev* sl = slots + rd.slot_begin;
+    const uint32_t ns = rd.slot_end - rd.slot_begin;
+    SlotDev* dst = results + blockIdx.x;
+    switch (rd.kind) {
+        case 0: reduce_work<1, false, false>(sl, ns, dst, red); break;
+        case 1: reduce_work<1, true, false>(sl, ns, dst, red); break;
+        case 2: reduce_work<1, false, true>(sl, ns, dst, red); break;
+        case 4: reduce_work<NPAY, false, false>(sl, ns, dst, red); break;
+        case 5: reduce_work<NPAY, true, false>(sl, ns, dst, red); break;
+        case 6: reduce_work<NPAY, false, true>(sl, ns, dst, red); break;
+        default: break;
     }
 }
 
@@ -348,10 +313,11 @@ hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev
     return hipGetLastError();
 }
 
+
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
-                         SlotDev* sums, SlotDev* compact) {
+                         SlotDev* results) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(n), dim3(REDUCE_THREADS), 0, st, slots, rds, n, sums, compact);
+    hipLaunchKernelGGL(k_reduce, dim3(n), dim3(REDUCE_THREADS), 0, st, slots, rds, results);
     return hipGetLastError();
 }
 

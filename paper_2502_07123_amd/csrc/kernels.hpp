@@ -87,8 +87,8 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
 hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev* tiles,
                           uint32_t n_tiles, const WorkDev* works, const LevelDev* levels);
 
-// sums[rd.sums] (+)= ordered sum of the work's tile slots; compact[w] = the result
+// results[w] = fixed-order sum of work w's tile slots (one block per work)
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
-                         SlotDev* sums, SlotDev* compact);
+                         SlotDev* results);
 
 }  // namespace mlmc

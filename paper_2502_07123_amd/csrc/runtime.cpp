@@ -57,16 +57,6 @@ void slot_to_sums(const SlotDev& s, int i, mlmc_sums& o) {
     o.nonfinite = s.nonfinite;
 }
 
-static mlmc_status ensure_pinned(mlmc_context* ctx, size_t bytes) {
-    if (ctx->pinned_bytes >= bytes) return MLMC_OK;
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    ctx->pinned = nullptr;
-    size_t want = std::max<size_t>(bytes, size_t(1) << 20);
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), want, hipHostMallocDefault));
-    ctx->pinned_bytes = want;
-    return MLMC_OK;
-}
-
 namespace {
 using VKey = std::tuple<int, int, int, int, bool, int>;
 VKey vkey(const Variant& v) { return VKey{v.est, v.arith, v.scheme, v.np, v.track, v.fields}; }
@@ -77,14 +67,118 @@ struct LaunchGroup {
     std::vector<uint32_t> works;
     uint32_t t0 = 0, t1 = 0, block = 0, lds = 0;
 };
+
+constexpr size_t MAX_FLIGHTS = 4;
+
+// a pinned staging buffer of at least `bytes`, not used by a flight in progress
+mlmc_status take_pinned(mlmc_context* ctx, size_t bytes, int& idx) {
+    idx = -1;
+    for (size_t i = 0; i < ctx->pins.size(); ++i)
+        if (!ctx->pins[i].busy && ctx->pins[i].bytes >= bytes) { idx = static_cast<int>(i); break; }
+    if (idx < 0) {
+        for (size_t i = 0; i < ctx->pins.size(); ++i)
+            if (!ctx->pins[i].busy) { idx = static_cast<int>(i); break; }
+        if (idx < 0) {
+            ctx->pins.emplace_back();
+            idx = static_cast<int>(ctx->pins.size() - 1);
+        }
+        PinnedBuf& pb = ctx->pins[idx];
+        if (pb.p) (void)hipHostFree(pb.p);
+        pb.p = nullptr;
+        pb.bytes = 0;
+        const size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pb.p), want, hipHostMallocDefault));
+        pb.bytes = want;
+    }
+    ctx->pins[idx].busy = true;
+    return MLMC_OK;
+}
+
+mlmc_status take_event(mlmc_context* ctx, bool timed, hipEvent_t& e) {
+    auto& pool = timed ? ctx->ev_timed : ctx->ev_plain;
+    if (!pool.empty()) {
+        e = pool.back();
+        pool.pop_back();
+        return MLMC_OK;
+    }
+    HIPCHK(hipEventCreateWithFlags(&e, timed ? hipEventDefault : hipEventDisableTiming));
+    return MLMC_OK;
+}
+
+void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
+    mlmc_kernel_stat* st = nullptr;
+    for (auto& x : ctx->stats)
+        if (x.estimator == v.est && x.arith == v.arith && x.scheme == v.scheme && x.fields == v.fields &&
+            x.payoffs == v.np && x.track == int(v.track))
+            st = &x;
+    if (!st) {
+        mlmc_kernel_stat z;
+        std::memset(&z, 0, sizeof(z));
+        z.estimator = v.est;
+        z.arith = v.arith;
+        z.scheme = v.scheme;
+        z.fields = v.fields;
+        z.payoffs = v.np;
+        z.track = v.track ? 1 : 0;
+        ctx->stats.push_back(z);
+        st = &ctx->stats.back();
+    }
+    st->launches += 1;
+    st->ms += ms;
+    st->path_steps += steps;
+}
 }  // namespace
 
-mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uint32_t n_sums,
-                      std::vector<SlotDev>& out) {
+// Waits for a flight, copies its results (to out, or to the mlmc_sums of its
+// enqueued work list) and returns its staging buffer and events to the pools.
+mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out) {
+    const hipError_t e = hipEventSynchronize(f.done);
+    ctx->ev_plain.push_back(f.done);
+    PinnedBuf& pb = ctx->pins[f.pin];
+    pb.busy = false;
+    if (e != hipSuccess) {
+        for (auto& g : f.timed) { ctx->ev_timed.push_back(g.e0); ctx->ev_timed.push_back(g.e1); }
+        return fail(ctx, MLMC_E_DEVICE, std::string("launch sequence failed: ") + hipGetErrorString(e));
+    }
+    const SlotDev* res = reinterpret_cast<const SlotDev*>(pb.p + f.down_off);
+    if (out) out->assign(res, res + f.n_works);
+    for (size_t i = 0; i < f.deliver.size(); ++i) {
+        const mlmc_level_work& w = f.deliver[i];
+        const uint32_t mask = f.masks[i];
+        const bool single = popcount32(mask) == 1;
+        int j = 0;
+        for (int p = 0; p < MLMC_NPAYOFF; ++p)
+            if ((mask >> p) & 1u) slot_to_sums(res[i], single ? 0 : p, w.out[j++]);
+    }
+    for (auto& g : f.timed) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, g.e0, g.e1));
+        add_stat(ctx, g.v, ms, g.steps);
+        ctx->ev_timed.push_back(g.e0);
+        ctx->ev_timed.push_back(g.e1);
+    }
+    return MLMC_OK;
+}
+
+// Lands every flight in order; their statuses wait in ctx->finished for
+// mlmc_level_sums_wait.  Returns the first failure.
+mlmc_status drain_flights(mlmc_context* ctx) {
+    mlmc_status first = MLMC_OK;
+    while (!ctx->flights.empty()) {
+        Flight f = std::move(ctx->flights.front());
+        ctx->flights.pop_front();
+        const mlmc_status s = land_flight(ctx, f, nullptr);
+        if (f.ticket) ctx->finished[f.ticket] = s;
+        if (s != MLMC_OK && first == MLMC_OK) first = s;
+    }
+    return first;
+}
+
+// Plans the works (levels, tables, tiles), places the plan in the workspace behind
+// the flights still in progress (landing the oldest when there is no room), uploads
+// it and launches the sequence.  Caller holds dev_mtx.
+mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works, Flight& f) {
     if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
-    out.clear();
-    if (works.empty()) return MLMC_OK;
-    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
     HIPCHK(hipSetDevice(ctx->device));
 
     // 1. levels, tables, works
@@ -121,12 +215,12 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
             li = it->second;
         }
         WorkDev& d = wdev[i];
+        std::memset(&d, 0, sizeof(d));
         d.lvl = li;
         d.c2 = stream_c2(w.level, w.est);
         d.c3 = w.option;
         d.k0 = static_cast<uint32_t>(w.seed);
         d.k1 = static_cast<uint32_t>(w.seed >> 32);
-        d.sums = w.sums;
         d.path_begin = w.path_begin;
         d.path_end = w.path_begin + w.n;
         d.debug = w.debug;
@@ -140,11 +234,17 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
         g.v = v;
         g.works.push_back(static_cast<uint32_t>(i));
     }
+    // longest chains first: a work's tiles start in the order of the tile list, so
+    // the fine levels (2^level sequential steps per path, few paths) go first and
+    // overlap the short, wide ones instead of forming the launch's tail
+    for (auto& kv : groups)
+        std::stable_sort(kv.second.works.begin(), kv.second.works.end(),
+                         [&](uint32_t a, uint32_t b) { return works[a].level > works[b].level; });
     std::vector<TileDev> tiles;
     std::vector<ReduceDev> reds(works.size());
     // works with few, long paths get their exact normals computed ahead (k_normals)
     std::vector<TileDev> ntiles[2];                 // [0]: FP64 normals, [1]: FP32
-    std::vector<size_t> zb_bytes(works.size(), 0), zb_off(works.size(), 0);
+    std::vector<size_t> zb_bytes(works.size(), 0);
     std::vector<int> zb_f32(works.size(), -1);
     for (auto& kv : groups) {
         LaunchGroup& g = kv.second;
@@ -202,8 +302,10 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
                 tiles.push_back(t);
             }
             reds[wi].slot_end = static_cast<uint32_t>(tiles.size());
-            reds[wi].sums = w.sums;
-            reds[wi].accumulate = w.accumulate ? 1u : 0u;
+            reds[wi].kind = (g.v.est == MLMC_EST_CORR ? 1u : 0u) |
+                            (g.v.est == MLMC_EST_APPROX && g.v.arith == MLMC_ARITH_FIXED ? 2u : 0u) |
+                            (g.v.np == NPAY ? 4u : 0u);
+            reds[wi].pad = 0;
             // table, plus the level-0 index histogram of the approximate estimator
             const LevelDev& Lw = levels[wdev[wi].lvl];
             g.lds = std::max<uint32_t>(
@@ -213,11 +315,10 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
     }
     if (tiles.size() >= (size_t(1) << 31)) return fail(ctx, MLMC_E_NOMEM, "too many tiles");
 
-    // 3. workspace layout:
-    //    [sums | compact | levels | works | tables | tiles | reds | normal tiles | slots | normals]
-    const size_t o_sums = 0;
-    const size_t o_comp = align_up(o_sums + size_t(n_sums) * sizeof(SlotDev), 256);
-    const size_t o_lvl = align_up(o_comp + works.size() * sizeof(SlotDev), 256);
+    // 3. layout (offsets from the flight's base):
+    //    [results | levels | works | tables | tiles | reds | normal tiles | slots | normals]
+    const size_t o_res = 0;
+    const size_t o_lvl = align_up(o_res + works.size() * sizeof(SlotDev), 256);
     const size_t o_work = align_up(o_lvl + levels.size() * sizeof(LevelDev), 256);
     const size_t o_tab = align_up(o_work + wdev.size() * sizeof(WorkDev), 256);
     const size_t o_tile = align_up(o_tab + tables.size(), 256);
@@ -226,24 +327,56 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
     const size_t o_nt1 = align_up(o_nt0 + ntiles[0].size() * sizeof(TileDev), 256);
     const size_t o_slot = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
     size_t o_zb = align_up(o_slot + tiles.size() * sizeof(SlotDev), 256);
+    std::vector<size_t> zb_off(works.size(), 0);
     for (size_t i = 0; i < works.size(); ++i) {
         if (zb_f32[i] < 0) continue;
         zb_off[i] = o_zb;
-        const uint64_t pos = works[i].n << works[i].level;
-        wdev[i].jbuf = reinterpret_cast<uint64_t>(ctx->ws + o_zb);
-        wdev[i].zbuf = reinterpret_cast<uint64_t>(ctx->ws + o_zb + align_up(pos * 4, 256));
         o_zb += zb_bytes[i];
     }
-    const size_t total = o_zb;
+    const size_t total = align_up(o_zb, 256);
     if (total > ctx->ws_bytes)
         return fail(ctx, MLMC_E_NOMEM, "workspace too small: need " + std::to_string(total) + " bytes");
+
+    // 4. place it: a ring over the workspace in flight order
+    if (ctx->flights.size() >= MAX_FLIGHTS) {
+        const mlmc_status s = drain_oldest(ctx);
+        if (s != MLMC_OK && ctx->poisoned) return s;
+    }
+    size_t base = 0;
+    for (;;) {
+        if (ctx->flights.empty()) { base = 0; break; }
+        const size_t head = ctx->flights.front().base;
+        const size_t tail = align_up(ctx->flights.back().end, 256);
+        const bool wrapped = ctx->flights.back().base < head;
+        if (!wrapped) {
+            if (tail + total <= ctx->ws_bytes) { base = tail; break; }
+            if (total <= head) { base = 0; break; }
+        } else if (tail + total <= head) {
+            base = tail;
+            break;
+        }
+        const mlmc_status s = drain_oldest(ctx);
+        if (s != MLMC_OK && ctx->poisoned) return s;
+    }
+    uint8_t* d = ctx->ws + base;
+    for (size_t i = 0; i < works.size(); ++i) {
+        if (zb_f32[i] < 0) continue;
+        const uint64_t pos = works[i].n << works[i].level;
+        wdev[i].jbuf = reinterpret_cast<uint64_t>(d + zb_off[i]);
+        wdev[i].zbuf = reinterpret_cast<uint64_t>(d + zb_off[i] + align_up(pos * 4, 256));
+    }
+
+    // 5. stage and upload [levels .. slots), launch, download the results
     const size_t up_bytes = o_slot - o_lvl;
     const size_t down_bytes = works.size() * sizeof(SlotDev);
-    mlmc_status st = ensure_pinned(ctx, std::max(up_bytes, down_bytes));
+    f.down_off = align_up(up_bytes, 256);
+    mlmc_status st = take_pinned(ctx, f.down_off + down_bytes, f.pin);
     if (st != MLMC_OK) return st;
-    // the pinned buffer may still be read by a previous copy: the stream is synchronised
-    // at the end of every run, so it is free here
-    uint8_t* h = ctx->pinned;
+    bool launched = false;
+    auto release = [&]() {
+        if (!launched) ctx->pins[f.pin].busy = false;
+    };
+    uint8_t* h = ctx->pins[f.pin].p;
     std::memset(h, 0, up_bytes);
     std::memcpy(h + (o_lvl - o_lvl), levels.data(), levels.size() * sizeof(LevelDev));
     std::memcpy(h + (o_work - o_lvl), wdev.data(), wdev.size() * sizeof(WorkDev));
@@ -252,85 +385,76 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uin
     std::memcpy(h + (o_red - o_lvl), reds.data(), reds.size() * sizeof(ReduceDev));
     if (!ntiles[0].empty()) std::memcpy(h + (o_nt0 - o_lvl), ntiles[0].data(), ntiles[0].size() * sizeof(TileDev));
     if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
-    uint8_t* d = ctx->ws;
     hipStream_t s = ctx->stream;
-    HIPCHK(hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s));
+    const hipError_t ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s);
+    if (ue != hipSuccess) {
+        release();
+        return fail(ctx, MLMC_E_DEVICE, std::string("upload: ") + hipGetErrorString(ue));
+    }
+    launched = true;                      // from here the staging buffer belongs to the flight
+    f.base = base;
+    f.end = base + total;
+    f.n_works = static_cast<uint32_t>(works.size());
+    if ((st = take_event(ctx, false, f.done)) != MLMC_OK) return st;
     // exact normals ahead of the path kernels for the buffered works
     const uint32_t ngrid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * 4;
-    for (int f = 0; f < 2; ++f) {
-        const uint32_t nn = static_cast<uint32_t>(ntiles[f].size());
+    for (int k = 0; k < 2; ++k) {
+        const uint32_t nn = static_cast<uint32_t>(ntiles[k].size());
         if (!nn) continue;
-        HIPCHK(launch_normals(f == 1, std::min(nn, ngrid), s,
-                              reinterpret_cast<const TileDev*>(d + (f ? o_nt1 : o_nt0)), nn,
+        HIPCHK(launch_normals(k == 1, std::min(nn, ngrid), s,
+                              reinterpret_cast<const TileDev*>(d + (k ? o_nt1 : o_nt0)), nn,
                               reinterpret_cast<const WorkDev*>(d + o_work),
                               reinterpret_cast<const LevelDev*>(d + o_lvl)));
     }
-
-    // 4. path kernels, one per variant, then the fixed-order reduction
+    // path kernels, one per variant, then the fixed-order reduction of each work
     const uint32_t max_grid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * ctx->tune.blocks_per_cu;
-    if (ctx->timing && ctx->events.size() < 2 * groups.size()) {
-        while (ctx->events.size() < 2 * groups.size()) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
-            ctx->events.push_back(e);
-        }
-    }
-    size_t gi = 0;
     for (auto& kv : groups) {
         LaunchGroup& g = kv.second;
         const uint32_t nt = g.t1 - g.t0;
         if (!nt) continue;
         const uint32_t grid = std::min(nt, max_grid);
-        if (ctx->timing) HIPCHK(hipEventRecord(ctx->events[2 * gi], s));
+        Flight::Timed tm{};
+        if (ctx->timing) {
+            tm.v = g.v;
+            for (uint32_t wi : g.works) tm.steps += works[wi].n << works[wi].level;
+            if ((st = take_event(ctx, true, tm.e0)) != MLMC_OK) return st;
+            if ((st = take_event(ctx, true, tm.e1)) != MLMC_OK) return st;
+            f.timed.push_back(tm);
+            HIPCHK(hipEventRecord(tm.e0, s));
+        }
         HIPCHK(launch_paths(g.vi, grid, g.block, g.lds, s,
                             reinterpret_cast<const TileDev*>(d + o_tile) + g.t0, nt,
                             reinterpret_cast<const WorkDev*>(d + o_work),
                             reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab,
                             reinterpret_cast<SlotDev*>(d + o_slot)));
-        if (ctx->timing) HIPCHK(hipEventRecord(ctx->events[2 * gi + 1], s));
-        ++gi;
+        if (ctx->timing) HIPCHK(hipEventRecord(tm.e1, s));
     }
-    HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s,
-                         reinterpret_cast<const SlotDev*>(d + o_slot),
-                         reinterpret_cast<const ReduceDev*>(d + o_red),
-                         reinterpret_cast<SlotDev*>(d + o_sums), reinterpret_cast<SlotDev*>(d + o_comp)));
-    HIPCHK(hipMemcpyAsync(h, d + o_comp, down_bytes, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    out.resize(works.size());
-    std::memcpy(out.data(), h, down_bytes);
-    if (ctx->timing) {
-        gi = 0;
-        for (auto& kv : groups) {
-            LaunchGroup& g = kv.second;
-            if (g.t1 == g.t0) continue;
-            float ms = 0.0f;
-            HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 * gi], ctx->events[2 * gi + 1]));
-            ++gi;
-            uint64_t steps = 0;
-            for (uint32_t wi : g.works) steps += works[wi].n << works[wi].level;
-            mlmc_kernel_stat* st = nullptr;
-            for (auto& x : ctx->stats)
-                if (x.estimator == g.v.est && x.arith == g.v.arith && x.scheme == g.v.scheme &&
-                    x.fields == g.v.fields && x.payoffs == g.v.np && x.track == int(g.v.track))
-                    st = &x;
-            if (!st) {
-                mlmc_kernel_stat z;
-                std::memset(&z, 0, sizeof(z));
-                z.estimator = g.v.est;
-                z.arith = g.v.arith;
-                z.scheme = g.v.scheme;
-                z.fields = g.v.fields;
-                z.payoffs = g.v.np;
-                z.track = g.v.track ? 1 : 0;
-                ctx->stats.push_back(z);
-                st = &ctx->stats.back();
-            }
-            st->launches += 1;
-            st->ms += ms;
-            st->path_steps += steps;
-        }
-    }
+    HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s, reinterpret_cast<const SlotDev*>(d + o_slot),
+                         reinterpret_cast<const ReduceDev*>(d + o_red), reinterpret_cast<SlotDev*>(d + o_res)));
+    HIPCHK(hipMemcpyAsync(h + f.down_off, d + o_res, down_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(f.done, s));
     return MLMC_OK;
+}
+
+mlmc_status drain_oldest(mlmc_context* ctx) {
+    if (ctx->flights.empty()) return MLMC_OK;
+    Flight f = std::move(ctx->flights.front());
+    ctx->flights.pop_front();
+    const mlmc_status s = land_flight(ctx, f, nullptr);
+    if (f.ticket) ctx->finished[f.ticket] = s;
+    return s;
+}
+
+mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, std::vector<SlotDev>& out) {
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    out.clear();
+    if (works.empty()) return MLMC_OK;
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    Flight f;
+    mlmc_status s = launch_flight(ctx, works, f);
+    if (s != MLMC_OK) return s;
+    s = land_flight(ctx, f, &out);
+    return s;
 }
 
 // ------------------------------------------------------------- adaptive MLMC
@@ -458,49 +582,88 @@ static mlmc_precision plain_precision(const OptionRun& o) {
     return p;
 }
 
-mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts, uint32_t n_sums) {
+void slot_accumulate(SlotDev& a, const SlotDev& b) {
+    for (int p = 0; p < NPAY; ++p) {
+        a.s1[p] += b.s1[p];
+        a.s2[p] += b.s2[p];
+        a.e1[p] += b.e1[p];
+        a.e2[p] += b.e2[p];
+        a.i1[p] += b.i1[p];
+        const uint64_t lo = a.i2lo[p] + b.i2lo[p];
+        a.i2hi[p] += b.i2hi[p] + (lo < a.i2lo[p] ? 1u : 0u);
+        a.i2lo[p] = lo;
+    }
+    a.n += b.n;
+    a.sat += b.sat;
+    a.nonfinite += b.nonfinite;
+}
+
+// run_works, split in halves while the workspace cannot hold the plan (a work's
+// sums do not depend on the other works of its launch)
+static mlmc_status run_works_split(mlmc_context* ctx, const std::vector<WorkSpec>& works,
+                                   std::vector<SlotDev>& out) {
+    mlmc_status s = run_works(ctx, works, out);
+    if (s != MLMC_E_NOMEM || works.size() < 2) return s;
+    const size_t h = works.size() / 2;
+    std::vector<SlotDev> a, b;
+    s = run_works_split(ctx, std::vector<WorkSpec>(works.begin(), works.begin() + h), a);
+    if (s != MLMC_OK) return s;
+    s = run_works_split(ctx, std::vector<WorkSpec>(works.begin() + h, works.end()), b);
+    if (s != MLMC_OK) return s;
+    out = std::move(a);
+    out.insert(out.end(), b.begin(), b.end());
+    return MLMC_OK;
+}
+
+mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, bool& ran) {
+    ran = false;
     std::vector<mlmc_precision> plain(opts.size());
-    for (size_t i = 0; i < opts.size(); ++i) plain[i] = plain_precision(*opts[i]);
+    std::vector<WorkSpec> works;
+    std::vector<std::pair<size_t, Pending>> who;
+    for (size_t i = 0; i < opts.size(); ++i) {
+        OptionRun& o = *opts[i];
+        if (o.done) continue;
+        plain[i] = plain_precision(o);
+        for (const Pending& p : option_advance(o)) {
+            WorkSpec w;
+            w.prob = &o.prob;
+            w.level = p.level;
+            w.prec = p.est == MLMC_EST_PLAIN ? &plain[i] : &o.cfg.prec[p.level];
+            w.est = p.est;
+            w.seed = o.seed;
+            w.option = o.option;
+            w.path_begin = o.sums[p.level][p.est].n;
+            w.n = p.n;
+            w.debug = 0;
+            works.push_back(w);
+            who.emplace_back(i, p);
+        }
+    }
+    if (works.empty()) return MLMC_OK;
+    ran = true;
+    std::vector<SlotDev> res;
+    const mlmc_status s = run_works_split(ctx, works, res);
+    if (s != MLMC_OK) return s;
+    std::vector<bool> counted(opts.size(), false);
+    for (size_t k = 0; k < works.size(); ++k) {
+        OptionRun& o = *opts[who[k].first];
+        const Pending& p = who[k].second;
+        slot_accumulate(o.sums[p.level][p.est], res[k]);
+        o.path_steps += p.n << p.level;
+        if (!counted[who[k].first]) { o.sweeps += 1; counted[who[k].first] = true; }
+    }
+    for (OptionRun* o : opts) {
+        o->saturations = 0;
+        for (auto& l : o->sums) for (auto& x : l) o->saturations += x.sat;
+    }
+    return MLMC_OK;
+}
+
+mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts) {
     for (;;) {
-        std::vector<WorkSpec> works;
-        std::vector<std::pair<size_t, Pending>> who;
-        for (size_t i = 0; i < opts.size(); ++i) {
-            OptionRun& o = *opts[i];
-            if (o.done) continue;
-            for (const Pending& p : option_advance(o)) {
-                WorkSpec w;
-                w.prob = &o.prob;
-                w.level = p.level;
-                w.prec = p.est == MLMC_EST_PLAIN ? &plain[i] : &o.cfg.prec[p.level];
-                w.est = p.est;
-                w.seed = o.seed;
-                w.option = o.option;
-                w.path_begin = o.sums[p.level][p.est].n;
-                w.n = p.n;
-                w.sums = o.sums_base + static_cast<uint32_t>(p.level) * 3u + static_cast<uint32_t>(p.est);
-                w.debug = 0;
-                w.accumulate = o.sums[p.level][p.est].n > 0;
-                works.push_back(w);
-                who.emplace_back(i, p);
-            }
-        }
-        if (works.empty()) return MLMC_OK;
-        // a (level, estimator) never touched before overwrites its device sums
-        std::vector<SlotDev> res;
-        const mlmc_status s = run_works(ctx, works, n_sums, res);
-        if (s != MLMC_OK) return s;
-        std::vector<bool> counted(opts.size(), false);
-        for (size_t k = 0; k < works.size(); ++k) {
-            OptionRun& o = *opts[who[k].first];
-            const Pending& p = who[k].second;
-            o.sums[p.level][p.est] = res[k];
-            o.path_steps += p.n << p.level;
-            if (!counted[who[k].first]) { o.sweeps += 1; counted[who[k].first] = true; }
-        }
-        for (OptionRun* o : opts) {
-            o->saturations = 0;
-            for (auto& a : o->sums) for (auto& s : a) o->saturations += s.sat;
-        }
+        bool ran = false;
+        const mlmc_status s = sweep_once(ctx, opts, ran);
+        if (s != MLMC_OK || !ran) return s;
     }
 }
 
@@ -541,7 +704,6 @@ mlmc_status estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* pr
         const mlmc_status s = validate_run(&probs[i], cfg, err);
         if (s != MLMC_OK) return fail(ctx, s, "option " + std::to_string(i) + ": " + err);
     }
-    const uint32_t per = static_cast<uint32_t>(cfg->L_max + 1) * 3u;
     std::vector<OptionRun> runs(n);
     std::vector<OptionRun*> ptrs(n);
     const double t0 = now_seconds();
@@ -550,12 +712,11 @@ mlmc_status estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* pr
         runs[i].cfg = *cfg;
         runs[i].seed = seed;
         runs[i].option = ids[i];
-        runs[i].sums_base = i * per;
         option_init(runs[i]);
         runs[i].t_start = t0;
         ptrs[i] = &runs[i];
     }
-    const mlmc_status s = run_sweeps(ctx, ptrs, n * per);
+    const mlmc_status s = run_sweeps(ctx, ptrs);
     if (s != MLMC_OK) return s;
     for (uint32_t i = 0; i < n; ++i) option_result(runs[i], out[i]);
     return MLMC_OK;
@@ -622,8 +783,14 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
 void mlmc_context_destroy(mlmc_context* ctx) {
     if (!ctx) return;
     mlmc_server_stop(ctx);
-    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    {
+        std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+        (void)drain_flights(ctx);
+    }
+    for (hipEvent_t e : ctx->ev_plain) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ev_timed) (void)hipEventDestroy(e);
+    for (auto& pb : ctx->pins)
+        if (pb.p) (void)hipHostFree(pb.p);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
 }
@@ -646,11 +813,9 @@ mlmc_status mlmc_level_sums(mlmc_context* ctx, const mlmc_problem* prob, int32_t
     w.option = option_id;
     w.path_begin = path_offset;
     w.n = n_paths;
-    w.sums = 0;
     w.debug = reinterpret_cast<uint64_t>(debug_paths);
-    w.accumulate = false;
     std::vector<SlotDev> res;
-    s = run_works(ctx, {w}, 1, res);
+    s = run_works(ctx, {w}, res);
     if (s != MLMC_OK) return s;
     const bool single = popcount32(prob->payoff_mask) == 1;
     int i = 0;
@@ -659,11 +824,10 @@ mlmc_status mlmc_level_sums(mlmc_context* ctx, const mlmc_problem* prob, int32_t
     return MLMC_OK;
 }
 
-mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works) {
-    if (!ctx) return MLMC_E_INVALID;
-    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+static mlmc_status batch_specs(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works,
+                               std::vector<WorkSpec>& ws) {
     if (!works || n == 0) return fail(ctx, MLMC_E_INVALID, "empty work list");
-    std::vector<WorkSpec> ws(n);
+    ws.resize(n);
     for (uint32_t i = 0; i < n; ++i) {
         const mlmc_level_work& w = works[i];
         if (w.struct_size != sizeof(mlmc_level_work)) return fail(ctx, MLMC_E_VERSION, "mlmc_level_work.struct_size mismatch");
@@ -671,11 +835,57 @@ mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_leve
         const mlmc_status s = validate_all(w.prob, w.level, w.n_paths, w.path_offset, w.prec, w.estimator, err);
         if (s != MLMC_OK) return fail(ctx, s, "work " + std::to_string(i) + ": " + err);
         if (!w.out) return fail(ctx, MLMC_E_INVALID, "work " + std::to_string(i) + ": out is NULL");
-        ws[i] = WorkSpec{w.prob, w.level, w.prec, w.estimator, w.seed, w.option_id, w.path_offset,
-                         w.n_paths, i, 0, false};
+        ws[i] = WorkSpec{w.prob, w.level, w.prec, w.estimator, w.seed, w.option_id, w.path_offset, w.n_paths, 0};
     }
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_level_sums_enqueue(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works,
+                                    uint64_t* ticket) {
+    if (!ctx || !ticket) return MLMC_E_INVALID;
+    *ticket = 0;
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    std::vector<WorkSpec> ws;
+    mlmc_status s = batch_specs(ctx, n, works, ws);
+    if (s != MLMC_OK) return s;
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    Flight f;
+    s = launch_flight(ctx, ws, f);
+    if (s != MLMC_OK) return s;
+    f.ticket = ctx->next_ticket++;
+    f.deliver.assign(works, works + n);
+    f.masks.resize(n);
+    for (uint32_t i = 0; i < n; ++i) f.masks[i] = works[i].prob->payoff_mask;
+    *ticket = f.ticket;
+    ctx->flights.push_back(std::move(f));
+    return MLMC_OK;
+}
+
+mlmc_status mlmc_level_sums_wait(mlmc_context* ctx, uint64_t ticket) {
+    if (!ctx) return MLMC_E_INVALID;
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    for (;;) {
+        auto it = ctx->finished.find(ticket);
+        if (it != ctx->finished.end()) {
+            const mlmc_status s = it->second;
+            ctx->finished.erase(it);
+            return s;
+        }
+        bool pending = false;
+        for (const Flight& f : ctx->flights) pending = pending || f.ticket == ticket;
+        if (!pending) return fail(ctx, MLMC_E_UNKNOWN_TICKET, "no such ticket");
+        (void)drain_oldest(ctx);
+    }
+}
+
+mlmc_status mlmc_level_sums_batch(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works) {
+    if (!ctx) return MLMC_E_INVALID;
+    if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    std::vector<WorkSpec> ws;
+    mlmc_status s = batch_specs(ctx, n, works, ws);
+    if (s != MLMC_OK) return s;
     std::vector<SlotDev> res;
-    const mlmc_status s = run_works(ctx, ws, n, res);
+    s = run_works(ctx, ws, res);
     if (s != MLMC_OK) return s;
     for (uint32_t i = 0; i < n; ++i) {
         const uint32_t mask = works[i].prob->payoff_mask;

@@ -44,12 +44,36 @@ struct WorkSpec {
     uint64_t seed;
     uint32_t option;
     uint64_t path_begin, n;
-    uint32_t sums;                  // index in the persistent sums region
     uint64_t debug;                 // device address of records or 0
-    bool accumulate;                // add onto the sums (false: overwrite them)
 };
 
 struct Server;
+
+struct PinnedBuf {
+    uint8_t* p = nullptr;
+    size_t bytes = 0;
+    bool busy = false;              // staging a flight that has not landed
+};
+
+// One launch sequence on the stream: its plan occupies workspace bytes
+// [base, end), its staging buffer holds the uploaded plan and, once `done` has
+// fired, the per-work results at down_off.
+struct Flight {
+    uint64_t ticket = 0;            // 0: an internal synchronous run
+    size_t base = 0, end = 0;
+    int pin = -1;
+    size_t down_off = 0;
+    uint32_t n_works = 0;
+    hipEvent_t done = nullptr;
+    struct Timed {
+        Variant v;
+        uint64_t steps = 0;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+    };
+    std::vector<Timed> timed;
+    std::vector<mlmc_level_work> deliver;   // enqueued batches: where results go
+    std::vector<uint32_t> masks;            // their payoff masks
+};
 
 }  // namespace mlmc
 
@@ -61,17 +85,20 @@ struct mlmc_context {
     uint64_t ws_bytes = 0;
     std::string err;
     bool poisoned = false;
-    uint8_t* pinned = nullptr;
-    size_t pinned_bytes = 0;
+    std::vector<mlmc::PinnedBuf> pins;
     int cu_count = 0;
     mlmc::Tuning tune;
     std::mutex dev_mtx;             // one launch sequence at a time on the device
     std::unique_ptr<mlmc::Server> server;
     // per-context cache of prepared levels (key: problem, level, precision, estimator)
     std::map<std::string, mlmc::LevelPrep> prep_cache;
+    // launch sequences in flight (oldest first) and statuses of landed tickets
+    std::deque<mlmc::Flight> flights;
+    std::map<uint64_t, mlmc_status> finished;
+    uint64_t next_ticket = 1;
+    std::vector<hipEvent_t> ev_plain, ev_timed;   // free events
     // kernel timing (HIP events around each path-kernel launch)
     bool timing = false;
-    std::vector<hipEvent_t> events;
     std::vector<mlmc_kernel_stat> stats;
     mlmc_context();                 // both defined where Server is complete
     ~mlmc_context();
@@ -81,12 +108,20 @@ namespace mlmc {
 
 mlmc_status fail(mlmc_context* ctx, mlmc_status s, const std::string& msg);
 
-// Runs the works as one launch sequence: path kernels (one per variant), the
-// reduction into sums[0 .. n_sums) of the workspace (added onto the previous
-// contents for works with accumulate), and a copy of each work's updated sums to
-// out (host, one SlotDev per work, in order).
-mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, uint32_t n_sums,
-                      std::vector<SlotDev>& out);
+// Runs the works as one launch sequence (path kernels, one per variant, each
+// work's sums reduced in a fixed order) and waits for it; out gets one SlotDev per
+// work, in order.  Flights already in progress stay in progress.
+mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, std::vector<SlotDev>& out);
+// The same split in two: launch_flight plans, places and launches (caller holds
+// dev_mtx and, for an enqueued batch, appends f to ctx->flights); land_flight waits
+// for it and delivers the results; drain_oldest / drain_flights land flights in
+// order, keeping their statuses in ctx->finished.
+mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works, Flight& f);
+mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out);
+mlmc_status drain_oldest(mlmc_context* ctx);
+mlmc_status drain_flights(mlmc_context* ctx);
+// a += b in a fixed field order (host side accumulation of sweep results)
+void slot_accumulate(SlotDev& a, const SlotDev& b);
 mlmc_status estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* probs,
                            const mlmc_run_config* cfg, uint64_t seed, const uint32_t* ids,
                            mlmc_result* out);
@@ -100,7 +135,6 @@ struct OptionRun {
     mlmc_run_config cfg;
     uint64_t seed = 0;
     uint32_t option = 0;
-    uint32_t sums_base = 0;         // first of (L_max + 1) * 3 sums
     int L = 0;
     bool done = false;
     int sweeps = 0;
@@ -118,7 +152,9 @@ struct Pending {
 };
 std::vector<Pending> option_advance(OptionRun& o);
 void option_result(const OptionRun& o, mlmc_result& r);
-mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts, uint32_t n_sums);
+mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts);
+// One sweep over the options that are not done (ran: whether any work was run).
+mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, bool& ran);
 double now_seconds();
 
 }  // namespace mlmc

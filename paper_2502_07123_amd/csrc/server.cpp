@@ -1,10 +1,10 @@
 // Continuous-batching server: a scheduler thread owns the device work of all
-// admitted requests.  Each iteration (a sweep) admits queued requests while a slot
-// and the workspace budget allow, asks every active request for its pending
+// admitted requests.  Each iteration (a sweep) admits queued requests while fewer
+// than max_active are active, asks every active request for its pending
 // samples (pilot, allocation top-up or a new level -- the adaptive driver of
 // Sections 2.1/2.2/6), runs all of them as one launch sequence, and retires the
 // requests that converged.  Requests submitted meanwhile join the next sweep.
-// Each request's sums live in its own region of the device sums table and its
+// Each request's sums are its own (added on the host in a fixed order) and its
 // uniforms depend only on (seed, option_id, level, estimator, path), so its
 // result does not depend on what else is in flight.
 #include <algorithm>
@@ -38,7 +38,6 @@ struct Server {
     std::vector<std::unique_ptr<Active>> active;
     std::map<uint64_t, mlmc_result> done;
     std::vector<uint32_t> free_slots;
-    uint32_t per_req = 0;          // sums per request
     uint32_t n_slots = 0;
     mlmc_status error = MLMC_OK;
     std::string error_msg;
@@ -66,7 +65,6 @@ void Server::loop() {
                 a->run.cfg.nested = q.req.nested;
                 a->run.seed = q.req.seed;
                 a->run.option = q.req.option_id;
-                a->run.sums_base = a->slot * per_req;
                 option_init(a->run);
                 a->run.t_start = q.t_submit;
                 active.push_back(std::move(a));
@@ -75,65 +73,29 @@ void Server::loop() {
         std::vector<OptionRun*> runs;
         for (auto& a : active) runs.push_back(&a->run);
         // one sweep: every active request's pending work in one launch sequence
-        std::vector<WorkSpec> works;
-        std::vector<std::pair<OptionRun*, Pending>> who;
-        std::vector<mlmc_precision> plain(runs.size());
-        for (size_t i = 0; i < runs.size(); ++i) {
-            OptionRun& o = *runs[i];
-            std::memset(&plain[i], 0, sizeof(plain[i]));
-            plain[i].struct_size = sizeof(mlmc_precision);
-            plain[i].arith = o.cfg.plain_arith;
-            plain[i].table_bits = 8;
-            for (const Pending& p : option_advance(o)) {
-                WorkSpec w;
-                w.prob = &o.prob;
-                w.level = p.level;
-                w.prec = p.est == MLMC_EST_PLAIN ? &plain[i] : &o.cfg.prec[p.level];
-                w.est = p.est;
-                w.seed = o.seed;
-                w.option = o.option;
-                w.path_begin = o.sums[p.level][p.est].n;
-                w.n = p.n;
-                w.sums = o.sums_base + static_cast<uint32_t>(p.level) * 3u + static_cast<uint32_t>(p.est);
-                w.debug = 0;
-                w.accumulate = o.sums[p.level][p.est].n > 0;
-                works.push_back(w);
-                who.emplace_back(&o, p);
+        bool ran = false;
+        const mlmc_status s = sweep_once(ctx, runs, ran);
+        if (s != MLMC_OK) {
+            std::lock_guard<std::mutex> lk(m);
+            error = s;
+            error_msg = ctx->err;
+            for (auto& a : active) {
+                mlmc_result r;
+                option_result(a->run, r);
+                r.status = s;
+                done[a->ticket] = r;
             }
-        }
-        if (!works.empty()) {
-            std::vector<SlotDev> res;
-            const mlmc_status s = run_works(ctx, works, n_slots * per_req, res);
-            if (s != MLMC_OK) {
-                std::lock_guard<std::mutex> lk(m);
-                error = s;
-                error_msg = ctx->err;
-                for (auto& a : active) {
-                    mlmc_result r;
-                    option_result(a->run, r);
-                    r.status = s;
-                    done[a->ticket] = r;
-                }
-                active.clear();
-                for (auto& q : queue) {
-                    mlmc_result r;
-                    std::memset(&r, 0, sizeof(r));
-                    r.struct_size = sizeof(r);
-                    r.status = s;
-                    done[q.ticket] = r;
-                }
-                queue.clear();
-                cv.notify_all();
-                return;
+            active.clear();
+            for (auto& q : queue) {
+                mlmc_result r;
+                std::memset(&r, 0, sizeof(r));
+                r.struct_size = sizeof(r);
+                r.status = s;
+                done[q.ticket] = r;
             }
-            std::map<OptionRun*, bool> counted;
-            for (size_t k = 0; k < works.size(); ++k) {
-                OptionRun& o = *who[k].first;
-                const Pending& p = who[k].second;
-                o.sums[p.level][p.est] = res[k];
-                o.path_steps += p.n << p.level;
-                if (!counted[&o]) { o.sweeps += 1; counted[&o] = true; }
-            }
+            queue.clear();
+            cv.notify_all();
+            return;
         }
         std::lock_guard<std::mutex> lk(m);
         for (auto it = active.begin(); it != active.end();) {
@@ -172,13 +134,9 @@ mlmc_status mlmc_server_start(mlmc_context* ctx, const mlmc_server_config* cfg) 
     auto srv = std::make_unique<Server>();
     srv->ctx = ctx;
     srv->cfg = *cfg;
-    srv->per_req = static_cast<uint32_t>(cfg->run.L_max + 1) * 3u;
-    // admission by memory: the sums of all slots plus room for one sweep's plan
-    const uint64_t per_bytes = uint64_t(srv->per_req) * sizeof(SlotDev);
-    const uint64_t reserve = std::min<uint64_t>(ctx->ws_bytes / 2, uint64_t(64) << 20);
-    const uint64_t fit = ctx->ws_bytes > reserve ? (ctx->ws_bytes - reserve) / per_bytes : 0;
-    srv->n_slots = static_cast<uint32_t>(std::min<uint64_t>(cfg->max_active, fit));
-    if (srv->n_slots == 0) return fail(ctx, MLMC_E_NOMEM, "workspace too small for one request");
+    // requests' sums are kept on the host; a sweep whose plan does not fit the
+    // workspace runs in parts
+    srv->n_slots = cfg->max_active;
     for (uint32_t i = srv->n_slots; i-- > 0;) srv->free_slots.push_back(i);
     Server* raw = srv.get();
     ctx->server = std::move(srv);

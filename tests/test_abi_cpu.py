@@ -66,6 +66,13 @@ def test_struct_layouts_match_the_header():
     assert int(out["off_res_level"]) == _lib.Result.level.offset
 
 
+def test_numpy_views_match_the_ctypes_structs():
+    for dt, cls in ((_lib.SUMS_DTYPE, _lib.Sums), (_lib.LEVELWORK_DTYPE, _lib.LevelWork)):
+        assert dt.itemsize == C.sizeof(cls)
+        for name, _ in cls._fields_:
+            assert dt.fields[name][1] == getattr(cls, name).offset, name
+
+
 GBM = dict(S0=100.0, K=100.0, r=0.05, sigma=0.2, T=1.0, barrier=85.0)
 
 
