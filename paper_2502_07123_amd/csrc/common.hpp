@@ -17,6 +17,10 @@ namespace mlmc {
 
 constexpr int NPAY = MLMC_NPAYOFF;
 
+// Largest per-index sample table (payoff slots x table entries, floats) kept in LDS
+// for level 0 of the FP32 approximate estimator; beyond it the index histogram.
+constexpr uint32_t YTAB_MAX_ENTRIES = 4096;
+
 // Device buffers whose addresses travel inside structs are global memory; naming
 // the address space lets the compiler use global (not flat) loads and stores, which
 // do not count against the LDS wait counter, so an LDS access does not have to wait

@@ -45,6 +45,19 @@ __host__ __device__ __forceinline__ double log_unit(double x) {
     return fma(de, LN2_HI, fma(de, LN2_LO, lm));
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// On the device the coefficients are read from constant memory at each use (scalar
+// loads into SGPRs) instead of being kept in vector registers across the kernels'
+// loops, where they would cost ~90 VGPRs of occupancy.
+static __constant__ double g_ninv64_pc[ninv64::DEG_C + 1] = NINV64_PC_INIT;
+static __constant__ double g_ninv64_pt[ninv64::DEG_T + 1] = NINV64_PT_INIT;
+#define NINV64_PC g_ninv64_pc
+#define NINV64_PT g_ninv64_pt
+#else
+#define NINV64_PC ninv64::PC
+#define NINV64_PT ninv64::PT
+#endif
+
 __host__ __device__ __forceinline__ double norminv_f64(uint32_t J) {
     using namespace ninv64;
     const int32_t sj = static_cast<int32_t>(J ^ 0x80000000u);
@@ -54,15 +67,15 @@ __host__ __device__ __forceinline__ double norminv_f64(uint32_t J) {
     const double w = -log_unit((us * (1.0 - us)) * 4.0);
     if (w < W1) {
         const double t = w - C_MID;
-        double p = PC[DEG_C];
+        double p = NINV64_PC[DEG_C];
 #pragma unroll
-        for (int k = DEG_C - 1; k >= 0; --k) p = fma(p, t, PC[k]);
+        for (int k = DEG_C - 1; k >= 0; --k) p = fma(p, t, NINV64_PC[k]);
         return y * p;
     }
     const double t = sqrt(w) - T_MID;
-    double p = PT[DEG_T];
+    double p = NINV64_PT[DEG_T];
 #pragma unroll
-    for (int k = DEG_T - 1; k >= 0; --k) p = fma(p, t, PT[k]);
+    for (int k = DEG_T - 1; k >= 0; --k) p = fma(p, t, NINV64_PT[k]);
     return copysign(p, y);
 }
 

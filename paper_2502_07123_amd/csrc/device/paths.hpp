@@ -516,6 +516,97 @@ struct PathBody {
         }
     }
 
+    // ---- level 0 of the FP32 approximate estimator from a table of per-index
+    // samples: Y(k) is computed once per level (ysample) into LDS and every path adds
+    // its own sample, so the sums equal those of the per-path code summed in the
+    // same order, with one table read per path instead of the path arithmetic.
+    // (Fixed point keeps the index histogram: its exact integer sums per path would
+    // cost more than a count.)
+    static constexpr bool YTAB = HIST && !FIXED;
+
+    // The level-0 sample of index k for each payoff slot (as a float: the FP32
+    // payoff difference, exact in FP64), written to ytab[slot * entries + k];
+    // returns false if one is not finite (the caller then counts instead).
+    __host__ __device__ __forceinline__ static bool ysample(const LevelDev& L, const void* tab,
+                                                            uint32_t k, float* ytab) {
+        FSide<ExactT> ex;
+        FSide<float> ap;
+        XSide ax;
+        level0_path(L, tab, k, ap, ax);
+        bool ok = true;
+#pragma unroll
+        for (int slot = 0; slot < NP; ++slot) {
+            const int p = NP == 1 ? L.payoff_single : slot;
+            float y = 0.0f;
+            if (NP == 1 || ((L.payoff_mask >> p) & 1u)) {
+                double Ye, Ya, Y;
+                int64_t Yint;
+                sample(L, p, ex, ap, ax, ExactT(0), ExactT(0), Ye, Ya, Yint, Y);
+                ok = ok && __builtin_isfinite(Y);
+                y = static_cast<float>(Y);
+            }
+            ytab[slot * L.table_entries + k] = y;
+        }
+        return ok;
+    }
+
+    // Adds the level-0 samples of group g (WPB paths, one Philox block) from the
+    // per-index table; partial groups and debug records take the checked loop.
+    __host__ __device__ __forceinline__ static void ytab_group(const LevelDev& L, const WorkDev& W,
+                                                               uint64_t g, const void* tab,
+                                                               const float* ytab, Acc<NP>& acc) {
+        const uint64_t path0 = g * WPB;
+        const u32x4 r = philox4x32_10(
+            u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+        const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+        const bool full = path0 >= W.path_begin && path0 + WPB <= W.path_end;
+        const int q = L.q;
+        const uint32_t E = L.table_entries;
+        if (full && !W.debug) {
+#pragma unroll
+            for (int wi = 0; wi < 4; ++wi)
+#pragma unroll
+                for (int fi = 0; fi < F; ++fi) {
+                    const uint32_t k = index_field(wd[wi], fi, q);
+#pragma unroll
+                    for (int slot = 0; slot < NP; ++slot) {
+                        const double Y = static_cast<double>(ytab[slot * E + k]);
+                        acc.s1[slot] += Y;
+                        acc.s2[slot] = fma(Y, Y, acc.s2[slot]);
+                    }
+                }
+            acc.n += WPB;
+            return;
+        }
+#pragma unroll
+        for (int wi = 0; wi < 4; ++wi) {
+#pragma unroll
+            for (int fi = 0; fi < F; ++fi) {
+                const uint32_t J = wd[wi];
+                const uint32_t k = index_field(J, fi, q);
+                const uint64_t pidx = path0 + uint64_t(wi * F + fi);
+                if (full || (pidx >= W.path_begin && pidx < W.path_end)) {
+                    if (W.debug) {
+                        FSide<ExactT> ex;
+                        FSide<float> ap;
+                        XSide ax;
+                        level0_path(L, tab, k, ap, ax);
+                        Acc<NP> scratch;
+                        acc_zero(scratch);
+                        finish(L, W, pidx, ex, ap, ax, J, k, scratch);
+                    }
+#pragma unroll
+                    for (int slot = 0; slot < NP; ++slot) {
+                        const double Y = static_cast<double>(ytab[slot * E + k]);
+                        acc.s1[slot] += Y;
+                        acc.s2[slot] = fma(Y, Y, acc.s2[slot]);
+                    }
+                    acc.n += 1;
+                }
+            }
+        }
+    }
+
     // Adds c copies of the level-0 sample of index k to acc.
     __host__ __device__ __forceinline__ static void hist_accumulate(const LevelDev& L,
                                                                     const void* tab, uint32_t k,

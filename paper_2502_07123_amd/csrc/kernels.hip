@@ -138,7 +138,9 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
     constexpr bool INTS = ARITH == MLMC_ARITH_FIXED && EST == MLMC_EST_APPROX;
     extern __shared__ __align__(16) uint8_t s_tab[];
     __shared__ RedLds red;
+    __shared__ uint32_t s_ybad;
     uint32_t cur = 0xFFFFFFFFu;
+    bool ytab = false;              // level-0 samples of the current level are in LDS
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileDev td = tiles[t];
         const WorkDev W = works[td.work];
@@ -148,13 +150,27 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
             const uint4* src = reinterpret_cast<const uint4*>(tables + L.table_off);
             uint4* dst = reinterpret_cast<uint4*>(s_tab);
             for (uint32_t i = threadIdx.x; i < (L.table_bytes >> 4); i += blockDim.x) dst[i] = src[i];
+            if (threadIdx.x == 0) s_ybad = 0u;
             __syncthreads();
             cur = W.lvl;
+            ytab = false;
+            if (Body::YTAB && L.level == 0 && uint32_t(NP) * L.table_entries <= YTAB_MAX_ENTRIES) {
+                // per-index samples of this level (after the step table)
+                float* yt = reinterpret_cast<float*>(s_tab + L.table_bytes);
+                for (uint32_t k = threadIdx.x; k < L.table_entries; k += blockDim.x)
+                    if (!Body::ysample(L, s_tab, k, yt)) s_ybad = 1u;
+                __syncthreads();
+                ytab = s_ybad == 0u;
+            }
         }
         Acc<NP> acc;
         acc_zero(acc);
         const uint64_t gend = td.group_begin + td.n_groups;
-        if (Body::HIST && L.level == 0) {
+        if (Body::YTAB && ytab && L.level == 0) {
+            const float* yt = reinterpret_cast<const float*>(s_tab + L.table_bytes);
+            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+                Body::ytab_group(L, W, g, s_tab, yt, acc);
+        } else if (Body::HIST && L.level == 0) {
             // level-0 approximate samples: count table indices in LDS, then add
             // c_k copies of each index's sample (thread t takes k = t, t + B, ...)
             uint32_t* hist = reinterpret_cast<uint32_t*>(s_tab + L.table_bytes);

@@ -306,10 +306,16 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
                             (g.v.est == MLMC_EST_APPROX && g.v.arith == MLMC_ARITH_FIXED ? 2u : 0u) |
                             (g.v.np == NPAY ? 4u : 0u);
             reds[wi].pad = 0;
-            // table, plus the level-0 index histogram of the approximate estimator
+            // table, plus the level-0 index histogram of the approximate estimator or
+            // (FP32, small enough) its per-index sample table
             const LevelDev& Lw = levels[wdev[wi].lvl];
-            g.lds = std::max<uint32_t>(
-                g.lds, Lw.table_bytes + (g.v.est == MLMC_EST_APPROX ? 4u * Lw.table_entries : 0u));
+            uint32_t extra = 0;
+            if (g.v.est == MLMC_EST_APPROX) {
+                extra = 4u * Lw.table_entries;
+                const uint32_t ys = static_cast<uint32_t>(g.v.np) * Lw.table_entries;
+                if (g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) extra = std::max(extra, 4u * ys);
+            }
+            g.lds = std::max<uint32_t>(g.lds, Lw.table_bytes + extra);
         }
         g.t1 = static_cast<uint32_t>(tiles.size());
     }
