@@ -95,11 +95,15 @@ typedef struct mlmc_problem {
  * or of the PLAIN generator.
  *   arith        PLAIN: FP64 or FP32 (exact normals in that precision).
  *                APPROX/CORR: FP32, FP16 or FIXED with Method-1 table normals;
- *                the exact side of CORR is always FP64 with FP64 normals.
+ *                the exact side of CORR is always FP64 with FP64 normals.  FP32
+ *                and FP16 evaluate Algorithm 1 operation by operation, each result
+ *                rounded to the type (IEEE nearest-even, no fused multiply-add);
+ *                constants and k, b are rounded once from their FP64 values.
  *   table_bits   q, 1..12: table of 2^q interval means indexed by the top q bits
  *                of the 32-bit uniform (Section 3.1, d = q).
  *   packed       APPROX only: take floor(32/q) q-bit indices per 32-bit word
- *                instead of one (the law of each index is the same).
+ *                instead of one (the law of each index is the same); FP32 with
+ *                q in {4, 6, 7, 8}, FP16 with q in {7, 8}.
  *   word_bits,   FIXED only, per variable (MLMC_V_*): two's-complement word w
  *   frac_bits    (2..32) and fractional bits f (0..62): value n 2^-f (Section 4.1,
  *                w = d + 1, f = d - e).  Every operation is rounded once to the
@@ -108,7 +112,16 @@ typedef struct mlmc_problem {
  *                use Z's format; the coarse sum of two normals keeps Z's f with one
  *                more integer bit; constants and k, b are quantised exactly from
  *                their FP64 values (con1 = r h, con2 = sigma * sqrt(h),
- *                con3 = ((0.5 * sigma) * sigma) * h, k = K / S0, b = B / S0). */
+ *                con3 = ((0.5 * sigma) * sigma) * h, k = K / S0, b = B / S0).
+ *   rng_method   APPROX/CORR: the approximate normals of Section 3 (0 or 1:
+ *                Method 1, the interval means; 2: Method 2 with two variables,
+ *                Z~_j = +-X_a +-X_b from a table of 2^(q/2-1) values fitted by least
+ *                squares under the sorting permutation pi, q even; the exact side of
+ *                CORR then uses the coupled uniform whose top q bits are pi(j);
+ *                3: Method 3, piecewise linear on the q - 1 dyadic intervals of
+ *                the magnitude bits).  The library expands Methods 2 and 3 into the
+ *                2^q-entry table (values formed in FP64, then rounded once to the
+ *                side's format).  PLAIN: must be 0 or 1. */
 typedef struct mlmc_precision {
     uint32_t struct_size;
     int32_t arith;
@@ -116,6 +129,8 @@ typedef struct mlmc_precision {
     int32_t packed;
     int32_t word_bits[MLMC_NVARS];
     int32_t frac_bits[MLMC_NVARS];
+    int32_t rng_method;
+    int32_t reserved;
 } mlmc_precision;
 
 /* Sums of one (level, estimator, payoff) over a set of paths (Section 2.1:
@@ -353,6 +368,14 @@ mlmc_status mlmc_server_stop(mlmc_context* ctx);
  * FP16 -> uint16_t[2^q] (binary16 bits); FIXED -> int32_t[2^q] with frac_bits
  * fractional bits.  out: host buffer.  Errors: MLMC_E_INVALID (q outside 1..16). */
 mlmc_status mlmc_build_table(int32_t q, int32_t arith, int32_t frac_bits, void* out);
+
+/* Methods 2 and 3 of Section 3 (see mlmc_precision.rng_method): values[2^q] (FP64,
+ * before rounding to a side's format) and, for Method 2, perm[2^q] (pi; NULL
+ * allowed; untouched for Method 3).  *iterations (NULL allowed): Method 2's
+ * least-squares solves until pi repeated.  Host buffers.  Errors: MLMC_E_INVALID
+ * (method not 2 or 3; q outside 2..12; odd q for Method 2). */
+mlmc_status mlmc_build_rng_table(int32_t q, int32_t method, double* values, uint16_t* perm,
+                                 int32_t* iterations);
 
 /* The 32-bit uniform word at stream position `word_index` (Philox4x32-10,
  * Salmon et al. 2011; counter (b mod 2^32, b div 2^32, level | estimator << 8,

@@ -16,10 +16,11 @@ Modules
               saturation (Section 4.1), as exact integer arithmetic.
   paths       coupled fine/coarse Euler-Maruyama (Section 2.1, Algorithm 1) and
               Milstein GBM paths in FP64 / FP32 / FP16 / fixed point, payoffs.
+  rngmethods  Methods 2 (sum of two small-table variables, least squares under a
+              permutation, permuted coupled uniform) and 3 (piecewise linear on
+              dyadic intervals) of Section 3.
   mlmc        per-level sums, the nested split (Section 2.2), optimal sample
               allocation (Sections 2.1-2.2) and the adaptive driver.
-  errmodel    rounding-error model: sensitivities and the V_indep / V_corr bounds
-              (Section 4.2-4.3), cost model and bit-width optimiser (Sections 5-6).
 
 Readings where the paper is silent are named R1..R23 in the docstrings; each is
 listed in the repository's design notes.

@@ -50,11 +50,13 @@ This module is test infrastructure: see the package docstring.
 from dataclasses import dataclass, field
 import math
 
+import mpmath
 import numpy as np
 
 from . import fixedpoint as fx
 from . import normal
 from .philox import StepWords, stream_words
+from . import rngmethods
 
 PAYOFFS = ("forward", "euro", "asian", "barrier", "digital")
 EST_PLAIN, EST_APPROX, EST_CORR = 0, 1, 2
@@ -79,9 +81,10 @@ class Problem:
 class Precision:
     """Arithmetic of the low-precision side.  fmt: var -> (w, f) for 'fixed'."""
     arith: str = "fp32"          # fp64 | fp32 | fp16 | fixed
-    q: int = 8                   # Method-1 table bits
+    q: int = 8                   # table bits (d of Section 3)
     packed: bool = False         # approx estimator: floor(32/q) indices per word
     fmt: tuple = ()              # tuple of (var, w, f) for 'fixed'
+    method: int = 1              # approximate normals: Method 1, 2 (n = 2) or 3
 
     def fmt_of(self, var):
         for v, w, f in self.fmt:
@@ -265,11 +268,28 @@ def make_side(arith, prec, c, scheme):
 
 
 # ------------------------------------------------------------------ normals
+def method_values(prec):
+    """FP64 table values of Method 2 or 3 (Section 3.2, 3.3) and Method 2's
+    permutation (None otherwise)."""
+    if prec.method == 2:
+        return rngmethods.method2_table(prec.q, 2)
+    if prec.method == 3:
+        return rngmethods.method3_table(prec.q), None
+    raise ValueError(prec.method)
+
+
 def side_table(side, prec):
-    """Method-1 table in the side's storage format."""
+    """The table of approximate normals in the side's storage format: Method 1's
+    exact values rounded once; Methods 2 and 3 their FP64 values rounded once."""
+    if prec.method == 1:
+        if isinstance(side, FixedSide):
+            return normal.table_fixed(prec.q, side.F["Z"][1])
+        return normal.table_float(prec.q, np.dtype(side.t).name)
+    vals, _ = method_values(prec)
     if isinstance(side, FixedSide):
-        return normal.table_fixed(prec.q, side.F["Z"][1])
-    return normal.table_float(prec.q, np.dtype(side.t).name)
+        f = side.F["Z"][1]
+        return np.array([normal.round_fixed(mpmath.mpf(float(v)), f) for v in vals], dtype=np.int64)
+    return vals.astype(side.t)
 
 
 # ------------------------------------------------------------------- paths
@@ -347,6 +367,9 @@ def simulate(prob: Problem, level: int, paths, prec: Precision, estimator: int,
         table = side_table(approx_side.side, prec)
 
     packed = prec.packed and estimator == EST_APPROX
+    perm = None
+    if estimator == EST_CORR and prec.method == 2:
+        perm = method_values(prec)[1]
     for step in range(N):
         if packed:
             idx = words.packed_index(step, prec.q)
@@ -354,7 +377,8 @@ def simulate(prob: Problem, level: int, paths, prec: Precision, estimator: int,
             J = words.word(step)
             idx = normal.table_index(J, prec.q)
         if exact_side is not None:
-            Z = normal.exact_normal(J)
+            # Method 2 couples the exact side to the permuted interval pi(j)
+            Z = normal.exact_normal(J if perm is None else rngmethods.coupled_words(J, prec.q, perm))
             exact_side.fine(Z.astype(exact_side.side.t), step)
         if approx_side is not None:
             approx_side.fine(table[idx], step)

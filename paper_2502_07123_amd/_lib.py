@@ -43,7 +43,7 @@ class Problem(C.Structure):
 class Precision(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("arith", C.c_int32), ("table_bits", C.c_int32),
                 ("packed", C.c_int32), ("word_bits", C.c_int32 * NVARS),
-                ("frac_bits", C.c_int32 * NVARS)]
+                ("frac_bits", C.c_int32 * NVARS), ("rng_method", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Sums(C.Structure):
@@ -170,6 +170,7 @@ def lib():
         "mlmc_poll": (st, [vp, u64, P(Result)]),
         "mlmc_server_stop": (st, [vp]),
         "mlmc_build_table": (st, [i32, i32, i32, vp]),
+        "mlmc_build_rng_table": (st, [i32, i32, P(C.c_double), P(C.c_uint16), P(i32)]),
         "mlmc_stream_words": (st, [u64, u32, i32, i32, u64, u64, P(u32)]),
         "mlmc_validate": (st, [P(Problem), i32, u64, u64, P(Precision), i32]),
         "mlmc_check_paths_host": (st, [P(Problem), i32, u64, u64, P(Precision), i32, u64, u32,
@@ -191,7 +192,7 @@ EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_c
             "mlmc_get_tuning", "mlmc_set_tuning",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_server_stop",
-            "mlmc_build_table", "mlmc_stream_words", "mlmc_validate", "mlmc_check_paths_host",
+            "mlmc_build_table", "mlmc_build_rng_table", "mlmc_stream_words", "mlmc_validate", "mlmc_check_paths_host",
             "mlmc_allocate")
 
 
@@ -205,13 +206,15 @@ def make_problem(scheme="euler", payoffs=("euro",), S0=100.0, K=100.0, r=0.05, s
                    S0, K, r, sigma, T, barrier)
 
 
-def make_precision(arith="fp32", q=8, packed=False, fmt=None):
-    """fmt: mapping var -> (word_bits, frac_bits) for 'fixed'."""
+def make_precision(arith="fp32", q=8, packed=False, fmt=None, method=1):
+    """fmt: mapping var -> (word_bits, frac_bits) for 'fixed'; method: approximate
+    normals of Section 3 (1, 2 or 3)."""
     p = Precision()
     p.struct_size = C.sizeof(Precision)
     p.arith = ARITH[arith]
     p.table_bits = q
     p.packed = 1 if packed else 0
+    p.rng_method = method
     if fmt:
         for v, (w, f) in dict(fmt).items():
             i = VARS.index(v)

@@ -49,6 +49,8 @@ struct LevelDev {
     double con1, con1c, con2, con3, k, b;
     // FP32 side (constants rounded to FP32; f2con3 = 2 con3 for the coarse cross term)
     float fcon1, fcon1c, fcon2, fcon3, fk, fb, f2con3, fpad;
+    // FP16 side (constants rounded once from FP64 to binary16)
+    _Float16 hcon1, hcon1c, hcon2, hcon3, hk, hb, hpad0, hpad1;
     // fixed-point side
     int64_t icon1, icon1c, icon2, icon3, ik, ib;
     int64_t izm_c2;           // the constant 2 in zsq's format
@@ -62,6 +64,9 @@ struct LevelDev {
     uint32_t table_entries;   // 2^q
     uint32_t table_off;       // byte offset of the step table in the table arena
     uint32_t table_bytes;
+    uint32_t perm_off;        // byte offset of Method 2's pi (uint16 per index) in the
+                              // level's table entry, 0 = none (exact side uses J)
+    uint32_t pad_perm;
 };
 
 struct WorkDev {

@@ -10,10 +10,9 @@
 // Low-precision side with Method-1 normals (Section 3.1).  The table holds, per
 // interval k, (Z~_k, s_k) with s_k the step multiplier the arithmetic would form
 // from Z~_k -- a function of k alone -- so the fine step is X <- X + X s_k:
-//   FP32:  s_k is the level's s from Z~_k rounded once to FP32; the coarse
-//          multiplier is s_a + s_b (+ 2 con3 Z~_a Z~_b), which equals the coarse s of
-//          Zs = Z~_a + Z~_b in exact arithmetic.  Paths agree with the per-operation
-//          FP32 reference to rounding (about 1e-6 relative).
+//   FP32 / FP16:  s_k is Algorithm 1's multiplier chain evaluated on Z~_k with each
+//          operation rounded to the side's type (built on the host); the coarse
+//          step runs the same chain on Zs = Z~_a + Z~_b.  Bit-exact by construction.
 //   FIXED: s_k is sum1 (Euler) or sum2 (Milstein) of Algorithm 1's chain in the
 //          per-variable formats, built on the host with the same rounding; the
 //          coarse step runs the whole chain on Zs.  Bit-exact by construction.
@@ -24,6 +23,7 @@
 #include <cmath>
 #include <cstdint>
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "../common.hpp"
 #include "fixed.hpp"
@@ -112,30 +112,60 @@ __host__ __device__ __forceinline__ void exact_step(FSide<double>& s, double Z, 
     }
 }
 
-// FP32 steps follow Algorithm 1 operation by operation, each rounded to FP32 (no
-// fused multiply-add), so FP32 paths are reproducible bit for bit.
-// The multiplier of one step from a normal z: mul1 = con2 z, sum1 = con1 + mul1
-// (Milstein: zsq = z z, zm1 = zsq - c, mul3 = con3 zm1, sum2 = sum1 + mul3).
-template <bool MIL>
-__host__ __device__ __forceinline__ float multiplier32(float z, float con1, float con2, float con3,
-                                                       float c) {
+// Low-precision float steps (FP32, FP16) follow Algorithm 1 operation by operation,
+// each rounded to the side's type (no fused multiply-add), so the paths are
+// reproducible bit for bit.  The multiplier of one step from a normal z:
+// mul1 = con2 z, sum1 = con1 + mul1 (Milstein: zsq = z z, zm1 = zsq - c,
+// mul3 = con3 zm1, sum2 = sum1 + mul3).
+template <bool MIL, typename T>
+__host__ __device__ __forceinline__ T multiplier_lp(T z, T con1, T con2, T con3, T c) {
 #pragma clang fp contract(off)
-    const float mul1 = con2 * z;
-    float s = con1 + mul1;
+    const T mul1 = con2 * z;
+    T s = con1 + mul1;
     if (MIL) {
-        const float zsq = z * z;
-        const float zm1 = zsq - c;
-        const float mul3 = con3 * zm1;
+        const T zsq = z * z;
+        const T zm1 = zsq - c;
+        const T mul3 = con3 * zm1;
         s = s + mul3;
     }
     return s;
 }
 
-__host__ __device__ __forceinline__ float advance32(float x, float s) {
+template <typename T>
+__host__ __device__ __forceinline__ T advance_lp(T x, T s) {
 #pragma clang fp contract(off)
-    const float mul2 = x * s;
+    const T mul2 = x * s;
     return x + mul2;
 }
+
+template <bool MIL>
+__host__ __device__ __forceinline__ float multiplier32(float z, float con1, float con2, float con3,
+                                                       float c) {
+    return multiplier_lp<MIL, float>(z, con1, con2, con3, c);
+}
+__host__ __device__ __forceinline__ float advance32(float x, float s) { return advance_lp<float>(x, s); }
+
+// The low-precision side's constants in its own type.
+template <typename T>
+struct LpConst {
+    T con1, con1c, con2, con3, k, b;
+};
+template <typename T>
+__host__ __device__ __forceinline__ LpConst<T> lp_const(const LevelDev& L);
+template <>
+__host__ __device__ __forceinline__ LpConst<float> lp_const<float>(const LevelDev& L) {
+    return LpConst<float>{L.fcon1, L.fcon1c, L.fcon2, L.fcon3, L.fk, L.fb};
+}
+template <>
+__host__ __device__ __forceinline__ LpConst<_Float16> lp_const<_Float16>(const LevelDev& L) {
+    return LpConst<_Float16>{L.hcon1, L.hcon1c, L.hcon2, L.hcon3, L.hk, L.hb};
+}
+
+// A step-table entry of a float side: (Z~_k, s_k) in the side's type.
+template <typename T>
+struct TabPair {
+    T z, s;
+};
 
 template <bool MIL>
 __host__ __device__ __forceinline__ void exact_step(FSide<float>& s, float Z, const LevelDev& L,
@@ -153,20 +183,21 @@ __host__ __device__ __forceinline__ void exact_step(FSide<float>& s, float Z, co
     }
 }
 
-// table step, FP32 low-precision side; entry = (Z~_k, s_k) with s_k the fine
-// multiplier of Z~_k (multiplier32 evaluated on the host)
-template <bool MIL>
-__host__ __device__ __forceinline__ void table_step(FSide<float>& s, float z, float sk,
-                                                    const LevelDev& L, bool coarse_on, bool odd,
-                                                    bool track) {
-    s.xf = advance32(s.xf, sk);
+// table step, float low-precision side; entry = (Z~_k, s_k) with s_k the fine
+// multiplier of Z~_k (multiplier_lp evaluated on the host)
+template <bool MIL, typename T>
+__host__ __device__ __forceinline__ void table_step(FSide<T>& s, T z, T sk, const LevelDev& L,
+                                                    bool coarse_on, bool odd, bool track) {
+    s.xf = advance_lp<T>(s.xf, sk);
     s.track_f(track);
     if (coarse_on) {
         if (!odd) {
             s.zp = z;
         } else {
-            const float zs = s.zp + z;
-            s.xc = advance32(s.xc, multiplier32<MIL>(zs, L.fcon1c, L.fcon2, L.fcon3, 2.0f));
+#pragma clang fp contract(off)
+            const LpConst<T> c = lp_const<T>(L);
+            const T zs = s.zp + z;
+            s.xc = advance_lp<T>(s.xc, multiplier_lp<MIL, T>(zs, c.con1c, c.con2, c.con3, T(2)));
             s.track_c(track);
         }
     }
@@ -245,8 +276,10 @@ struct PathBody {
     static constexpr bool FIXED = ARITH == MLMC_ARITH_FIXED;
     static constexpr bool PLAIN32 = EST == MLMC_EST_PLAIN && ARITH == MLMC_ARITH_FP32;
     // table entry: FP32 Euler needs only s_k; the others (Z~_k, s_k)
-    static constexpr bool TAB_PAIR = true;       // (Z~_k, s_k): the coarse chain needs Z~
-    static constexpr int TAB_BYTES = !HAS_TABLE ? 0 : 8;
+    static constexpr bool HALF = ARITH == MLMC_ARITH_FP16;
+    // the float low-precision side's type (FP16 or FP32)
+    using AT = typename std::conditional<HALF, _Float16, float>::type;
+    static constexpr int TAB_BYTES = !HAS_TABLE ? 0 : (HALF ? 4 : 8);
     using ExactT = typename std::conditional<PLAIN32, float, double>::type;
 
     // tab: table of 2^q entries (LDS on the device, host memory in checks)
@@ -264,7 +297,7 @@ struct PathBody {
         uint64_t blk = g * nblk;
 
         FSide<ExactT> ex;
-        FSide<float> ap;
+        FSide<AT> ap;
         XSide ax;
         uint32_t first_word = 0, first_index = 0;
 
@@ -297,6 +330,16 @@ struct PathBody {
         }
     }
 
+    // The word whose uniform the exact side inverts: J itself, or (Method 2) J with
+    // its top q bits replaced by pi(top q bits) -- pi in the level's table entry.
+    __host__ __device__ __forceinline__ static uint32_t coupled_word(const LevelDev& L, const void* tab,
+                                                                     uint32_t J) {
+        if (EST != MLMC_EST_CORR || !L.perm_off) return J;
+        const uint16_t* pi = reinterpret_cast<const uint16_t*>(static_cast<const uint8_t*>(tab) + L.perm_off);
+        const int sh = 32 - L.q;
+        return (uint32_t(pi[J >> sh]) << sh) | (J & ((1u << sh) - 1u));
+    }
+
     // Table index in field fi of a uniform word: q bits, fields from the most
     // significant end (F == 1: the top q bits).
     __host__ __device__ __forceinline__ static uint32_t index_field(uint32_t J, int fi, int q) {
@@ -312,7 +355,7 @@ struct PathBody {
     // unrolled since 4F is even); J the word holding it, fi its field.
     __host__ __device__ __forceinline__ static void step(
         const LevelDev& L, const WorkDev& W, const void* tab, uint32_t sl, bool odd, uint32_t J,
-        int fi, uint64_t path0, FSide<ExactT>& ex, FSide<float>& ap, XSide& ax,
+        int fi, uint64_t path0, FSide<ExactT>& ex, FSide<AT>& ap, XSide& ax,
         uint32_t& first_word, uint32_t& first_index, Acc<NP>& acc) {
         const int lev = L.level;
         const uint32_t N = 1u << lev;
@@ -328,18 +371,15 @@ struct PathBody {
         if (n == 0) { first_word = J; first_index = k; }
         if (HAS_EXACT) {
             if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J), L, coarse_on, odd, TRACK);
-            else exact_step<MIL>(ex, norminv_f64(J), L, coarse_on, odd, TRACK);
+            else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J)), L, coarse_on, odd, TRACK);
         }
         if (HAS_TABLE) {
             if (FIXED) {
                 const int2 e = static_cast<const int2*>(tab)[k];
                 fixed_step<MIL>(ax, e.x, e.y, L, coarse_on, odd, TRACK);
-            } else if (TAB_PAIR) {
-                const float2 e = static_cast<const float2*>(tab)[k];
-                table_step<MIL>(ap, e.x, e.y, L, coarse_on, odd, TRACK);
             } else {
-                const float sk = static_cast<const float*>(tab)[k];
-                table_step<MIL>(ap, 0.0f, sk, L, coarse_on, odd, TRACK);
+                const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k];
+                table_step<MIL, AT>(ap, e.z, e.s, L, coarse_on, odd, TRACK);
             }
         }
         if (n == N - 1u) {
@@ -358,7 +398,7 @@ struct PathBody {
     template <uint32_t AH>
     __host__ __device__ __forceinline__ static void buffered_steps(
         const LevelDev& L, uint32_t N, uint64_t P, uint64_t col, const MLMC_GLOBAL uint32_t* Jb,
-        const MLMC_GLOBAL ExactT* Zb, const void* tab, FSide<ExactT>& ex, FSide<float>& ap, XSide& ax) {
+        const MLMC_GLOBAL ExactT* Zb, const void* tab, FSide<ExactT>& ex, FSide<AT>& ap, XSide& ax) {
         const int q = L.q;
         uint32_t jq[AH];
         ExactT zq[AH];
@@ -382,8 +422,8 @@ struct PathBody {
                         const int2 e = static_cast<const int2*>(tab)[k];
                         fixed_step<MIL>(ax, e.x, e.y, L, true, (h & 1u) == 1u, TRACK);
                     } else {
-                        const float2 e = static_cast<const float2*>(tab)[k];
-                        table_step<MIL>(ap, e.x, e.y, L, true, (h & 1u) == 1u, TRACK);
+                        const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k];
+                        table_step<MIL, AT>(ap, e.z, e.s, L, true, (h & 1u) == 1u, TRACK);
                     }
                 }
             }
@@ -402,7 +442,7 @@ struct PathBody {
         const MLMC_GLOBAL uint32_t* Jb = global_ptr<const uint32_t>(W.jbuf);
         const int q = L.q;
         FSide<ExactT> ex;
-        FSide<float> ap;
+        FSide<AT> ap;
         XSide ax;
         ex.init();
         if (HAS_TABLE) { if (FIXED) ax.init(L); else ap.init(); }
@@ -421,7 +461,7 @@ struct PathBody {
     // integer), Y (the estimator's sample).
     __host__ __device__ __forceinline__ static void sample(const LevelDev& L, int p,
                                                            const FSide<ExactT>& ex,
-                                                           const FSide<float>& ap, XSide& ax,
+                                                           const FSide<AT>& ap, XSide& ax,
                                                            ExactT ek, ExactT eb, double& Ye,
                                                            double& Ya, int64_t& Yint, double& Y) {
         const int lev = L.level;
@@ -440,9 +480,11 @@ struct PathBody {
                 Yint = pf - pc;
                 Ya = ldexp(static_cast<double>(Yint), -L.fX);
             } else {
-                const float pf = ap.payoff(p, true, lev, L.fk, L.fb);
-                const float pc = lev ? ap.payoff(p, false, lev - 1, L.fk, L.fb) : 0.0f;
-                const float y = pf - pc;
+#pragma clang fp contract(off)
+                const LpConst<AT> c = lp_const<AT>(L);
+                const AT pf = ap.payoff(p, true, lev, c.k, c.b);
+                const AT pc = lev ? ap.payoff(p, false, lev - 1, c.k, c.b) : AT(0);
+                const AT y = pf - pc;
                 Ya = static_cast<double>(y);
             }
         }
@@ -459,7 +501,7 @@ struct PathBody {
 
     // the level-0 path of index k (its final states)
     __host__ __device__ __forceinline__ static void level0_path(const LevelDev& L, const void* tab,
-                                                                uint32_t k, FSide<float>& ap,
+                                                                uint32_t k, FSide<AT>& ap,
                                                                 XSide& ax) {
         if (FIXED) {
             ax.init(L);
@@ -467,8 +509,8 @@ struct PathBody {
             fixed_step<MIL>(ax, e.x, e.y, L, false, false, TRACK);
         } else {
             ap.init();
-            const float2 e = static_cast<const float2*>(tab)[k];
-            table_step<MIL>(ap, e.x, e.y, L, false, false, TRACK);
+            const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k];
+            table_step<MIL, AT>(ap, e.z, e.s, L, false, false, TRACK);
         }
     }
 
@@ -504,7 +546,7 @@ struct PathBody {
                     count(k);
                     if (W.debug) {
                         FSide<ExactT> ex;
-                        FSide<float> ap;
+                        FSide<AT> ap;
                         XSide ax;
                         level0_path(L, tab, k, ap, ax);
                         Acc<NP> scratch;
@@ -530,7 +572,7 @@ struct PathBody {
     __host__ __device__ __forceinline__ static bool ysample(const LevelDev& L, const void* tab,
                                                             uint32_t k, float* ytab) {
         FSide<ExactT> ex;
-        FSide<float> ap;
+        FSide<AT> ap;
         XSide ax;
         level0_path(L, tab, k, ap, ax);
         bool ok = true;
@@ -588,7 +630,7 @@ struct PathBody {
                 if (full || (pidx >= W.path_begin && pidx < W.path_end)) {
                     if (W.debug) {
                         FSide<ExactT> ex;
-                        FSide<float> ap;
+                        FSide<AT> ap;
                         XSide ax;
                         level0_path(L, tab, k, ap, ax);
                         Acc<NP> scratch;
@@ -612,7 +654,7 @@ struct PathBody {
                                                                     const void* tab, uint32_t k,
                                                                     uint32_t c, Acc<NP>& acc) {
         FSide<ExactT> ex;
-        FSide<float> ap;
+        FSide<AT> ap;
         XSide ax;
         level0_path(L, tab, k, ap, ax);
         const double cd = static_cast<double>(c);
@@ -647,7 +689,7 @@ struct PathBody {
 
     __host__ __device__ __forceinline__ static void finish(const LevelDev& L, const WorkDev& W,
                                                            uint64_t pidx, const FSide<ExactT>& ex,
-                                                           const FSide<float>& ap, XSide& ax,
+                                                           const FSide<AT>& ap, XSide& ax,
                                                            uint32_t first_word,
                                                            uint32_t first_index, Acc<NP>& acc) {
         const int lev = L.level;

@@ -5,6 +5,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -49,10 +50,18 @@ static long double quantile_ld(uint64_t k, int q) {
     return upper ? -x : x;
 }
 
+// one lock for the table caches (Method 1 and Methods 2/3)
+static std::mutex g_tables_mtx;
+static const std::vector<long double>& method1_table_nolock(int q);
+
 const std::vector<long double>& method1_table(int q) {
-    static std::mutex mtx;
+    std::lock_guard<std::mutex> lock(g_tables_mtx);
+    return method1_table_nolock(q);
+}
+
+// callers hold g_tables_mtx
+static const std::vector<long double>& method1_table_nolock(int q) {
     static std::map<int, std::vector<long double>> cache;
-    std::lock_guard<std::mutex> lock(mtx);
     auto it = cache.find(q);
     if (it != cache.end()) return it->second;
     const uint64_t n = uint64_t(1) << q;
@@ -76,6 +85,150 @@ const std::vector<long double>& method1_table(int q) {
     return cache.emplace(q, std::move(T)).first->second;
 }
 
+// ------------------------------------------------ Methods 2 and 3 (Section 3)
+// Method 2 (n = 2): j = (chunk 0, chunk 1) of m = q/2 bits each; a chunk with top
+// bit s and other bits r contributes +X[r] (s = 1) or -X[M-1-r] (s = 0), M = 2^(m-1)
+// (the sign-bit form of Method 1); Z~_j is the sum of the two contributions.  X
+// starts as the upper half of the m-bit Method-1 table over sqrt(2); then the Z~
+// are ranked (pi(j), ties by j) and X is refitted by least squares against the
+// q-bit Method-1 values at pi(j), until pi repeats.  The exact side's uniform takes
+// pi(j) as its top q bits.
+// Method 3: j = (s, r), r's dyadic interval i = max(1, bit length of r) (intervals
+// {0,1}, [2,3], [4,7], ...: q - 1 pairs); on the lower half Z = a_i + b_i r fitted
+// by least squares to the Method-1 values, the upper half by antisymmetry.
+// Values are formed in FP64 (inputs: the Method-1 values rounded to FP64; fits in
+// long double), the precision in which the table builder then rounds them.
+namespace {
+void m2_chunks(uint32_t j, int q, int m, uint32_t M, uint32_t col[2], double sgn[2]) {
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t chunk = (j >> (q - m * (c + 1))) & ((1u << m) - 1u);
+        const uint32_t s = chunk >> (m - 1), r = chunk & (M - 1u);
+        col[c] = s ? r : M - 1u - r;
+        sgn[c] = s ? 1.0 : -1.0;
+    }
+}
+// values of the two chunks added in ascending order of value
+double m2_value(const std::vector<double>& X, const uint32_t col[2], const double sgn[2]) {
+    double a = sgn[0] * X[col[0]], b = sgn[1] * X[col[1]];
+    if (b < a) std::swap(a, b);
+    return a + b;
+}
+std::vector<uint32_t> ranks_of(const std::vector<double>& v) {
+    std::vector<uint32_t> order(v.size());
+    for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return v[a] < v[b]; });
+    std::vector<uint32_t> r(v.size());
+    for (uint32_t i = 0; i < order.size(); ++i) r[order[i]] = i;
+    return r;
+}
+// least squares by the normal equations, Gaussian elimination with partial pivoting
+std::vector<long double> solve_spd(std::vector<long double> A, std::vector<long double> b, size_t M) {
+    for (size_t c = 0; c < M; ++c) {
+        size_t piv = c;
+        for (size_t r = c + 1; r < M; ++r)
+            if (fabsl(A[r * M + c]) > fabsl(A[piv * M + c])) piv = r;
+        if (piv != c) {
+            for (size_t k = 0; k < M; ++k) std::swap(A[c * M + k], A[piv * M + k]);
+            std::swap(b[c], b[piv]);
+        }
+        for (size_t r = c + 1; r < M; ++r) {
+            const long double f = A[r * M + c] / A[c * M + c];
+            for (size_t k = c; k < M; ++k) A[r * M + k] -= f * A[c * M + k];
+            b[r] -= f * b[c];
+        }
+    }
+    std::vector<long double> x(M);
+    for (size_t c = M; c-- > 0;) {
+        long double t = b[c];
+        for (size_t k = c + 1; k < M; ++k) t -= A[c * M + k] * x[k];
+        x[c] = t / A[c * M + c];
+    }
+    return x;
+}
+}  // namespace
+
+const MethodTable& method_table(int q, int method) {
+    static std::map<std::pair<int, int>, MethodTable> cache;
+    std::lock_guard<std::mutex> lock(g_tables_mtx);
+    auto it = cache.find({q, method});
+    if (it != cache.end()) return it->second;
+    const uint32_t n = 1u << q;
+    std::vector<double> T(n);
+    const auto& Tld = method1_table_nolock(q);
+    for (uint32_t k = 0; k < n; ++k) T[k] = static_cast<double>(Tld[k]);
+    MethodTable out;
+    out.z.assign(n, 0.0);
+    if (method == 2) {
+        const int m = q / 2;
+        const uint32_t M = 1u << (m - 1);
+        const auto& Hm = method1_table_nolock(m);
+        std::vector<double> X(M);
+        for (uint32_t r = 0; r < M; ++r) X[r] = static_cast<double>(Hm[M + r]) / std::sqrt(2.0);
+        std::vector<uint32_t> pi;
+        for (int iter = 0;; ++iter) {
+            for (uint32_t j = 0; j < n; ++j) {
+                uint32_t col[2];
+                double sg[2];
+                m2_chunks(j, q, m, M, col, sg);
+                out.z[j] = m2_value(X, col, sg);
+            }
+            std::vector<uint32_t> r = ranks_of(out.z);
+            if (r == pi || iter > 5000) {
+                out.iterations = iter;                   // least-squares solves made
+                break;
+            }
+            pi = std::move(r);
+            std::vector<long double> AtA(size_t(M) * M, 0.0L), Atb(M, 0.0L);
+            for (uint32_t j = 0; j < n; ++j) {
+                uint32_t col[2];
+                double sg[2];
+                m2_chunks(j, q, m, M, col, sg);
+                const long double t = T[pi[j]];
+                for (int a = 0; a < 2; ++a) {
+                    Atb[col[a]] += sg[a] * t;
+                    for (int b = 0; b < 2; ++b) AtA[size_t(col[a]) * M + col[b]] += sg[a] * sg[b];
+                }
+            }
+            const std::vector<long double> x = solve_spd(AtA, Atb, M);
+            for (uint32_t k = 0; k < M; ++k) X[k] = static_cast<double>(x[k]);
+        }
+        out.perm.resize(n);
+        for (uint32_t j = 0; j < n; ++j) out.perm[j] = static_cast<uint16_t>(pi[j]);
+    } else {
+        const uint32_t half = n / 2;
+        std::vector<double> a(q, 0.0), b(q, 0.0);
+        auto interval = [](uint32_t r) {
+            int bl = 0;
+            while (r >> bl) ++bl;
+            return bl < 1 ? 1 : bl;
+        };
+        for (int i = 1; i < q; ++i) {
+            const uint32_t lo = i == 1 ? 0u : (1u << (i - 1)), hi = (1u << i) - 1u;
+            long double sr = 0, sz = 0;
+            const long double cnt = static_cast<long double>(hi - lo + 1);
+            for (uint32_t r = lo; r <= hi; ++r) { sr += r; sz += T[r]; }
+            const long double rm = sr / cnt, zm = sz / cnt;
+            long double sxy = 0, sxx = 0;
+            for (uint32_t r = lo; r <= hi; ++r) {
+                sxy += (r - rm) * (T[r] - zm);
+                sxx += (r - rm) * (r - rm);
+            }
+            const long double bb = sxy / sxx;
+            a[i] = static_cast<double>(zm - bb * rm);
+            b[i] = static_cast<double>(bb);
+        }
+        for (uint32_t j = 0; j < n; ++j) {
+            const bool up = j >= half;
+            const uint32_t rr = up ? n - 1u - j : j;
+            const int i = interval(rr);
+            const double prod = b[i] * static_cast<double>(rr);
+            const double low = a[i] + prod;
+            out.z[j] = up ? -low : low;
+        }
+    }
+    return cache.emplace(std::make_pair(q, method), std::move(out)).first->second;
+}
+
 static uint16_t to_half_bits(long double x) {
     // round-to-nearest-even to IEEE binary16 (normal and subnormal; no overflow here)
     const uint16_t sign = std::signbit(x) ? 0x8000u : 0u;
@@ -92,6 +245,14 @@ static uint16_t to_half_bits(long double x) {
     const uint32_t mant = static_cast<uint32_t>(mm);
     if (mant < 1024u) return static_cast<uint16_t>(sign | mant);   // subnormal
     return static_cast<uint16_t>(sign | ((ee + 15) << 10) | (mant - 1024u));
+}
+
+// x rounded once to binary16 (from the exact value of x)
+static _Float16 half_of(long double x) {
+    const uint16_t b = to_half_bits(x);
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return h;
 }
 
 static bool quantize_ld(long double x, int f, int w, int64_t& out) {
@@ -178,15 +339,20 @@ mlmc_status validate_precision(const mlmc_precision* prec, int estimator, const 
     if (estimator == MLMC_EST_PLAIN) {
         if (prec->arith != MLMC_ARITH_FP64 && prec->arith != MLMC_ARITH_FP32) { err = "PLAIN supports FP64 and FP32"; return MLMC_E_INVALID; }
         if (prec->packed) { err = "packed indices apply to APPROX only"; return MLMC_E_INVALID; }
+        if (prec->rng_method > 1) { err = "PLAIN uses exact normals: rng_method must be 0 or 1"; return MLMC_E_INVALID; }
         return MLMC_OK;
     }
-    if (prec->arith != MLMC_ARITH_FP32 && prec->arith != MLMC_ARITH_FIXED) { err = "APPROX/CORR support FP32 and FIXED arithmetic"; return MLMC_E_INVALID; }
+    if (prec->arith != MLMC_ARITH_FP32 && prec->arith != MLMC_ARITH_FP16 && prec->arith != MLMC_ARITH_FIXED) { err = "APPROX/CORR support FP32, FP16 and FIXED arithmetic"; return MLMC_E_INVALID; }
     if (prec->table_bits < 1 || prec->table_bits > 12) { err = "table_bits must be 1..12"; return MLMC_E_INVALID; }
+    if (prec->rng_method < 0 || prec->rng_method > 3) { err = "rng_method must be 0..3"; return MLMC_E_INVALID; }
+    if (prec->rng_method == 2 && (prec->table_bits % 2 || prec->table_bits < 2)) { err = "Method 2 needs an even table_bits >= 2"; return MLMC_E_INVALID; }
+    if (prec->rng_method == 3 && prec->table_bits < 2) { err = "Method 3 needs table_bits >= 2"; return MLMC_E_INVALID; }
     if (prec->packed) {
         if (estimator != MLMC_EST_APPROX) { err = "packed indices apply to APPROX only"; return MLMC_E_INVALID; }
-        if (prec->arith != MLMC_ARITH_FP32) { err = "packed indices need FP32 arithmetic"; return MLMC_E_INVALID; }
+        if (prec->arith != MLMC_ARITH_FP32 && prec->arith != MLMC_ARITH_FP16) { err = "packed indices need FP32 or FP16 arithmetic"; return MLMC_E_INVALID; }
         const int F = 32 / prec->table_bits;
         if (F != 4 && F != 5 && F != 8) { err = "packed indices need table_bits in {4, 6, 7, 8}"; return MLMC_E_INVALID; }
+        if (prec->arith == MLMC_ARITH_FP16 && F != 4) { err = "packed FP16 indices need table_bits 7 or 8"; return MLMC_E_INVALID; }
     }
     if (prec->arith != MLMC_ARITH_FIXED) return MLMC_OK;
     const bool mil = p->scheme == MLMC_MILSTEIN;
@@ -262,6 +428,12 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
     L.f2con3 = static_cast<float>(2.0 * L.con3);
     L.fk = static_cast<float>(L.k);
     L.fb = static_cast<float>(L.b);
+    L.hcon1 = half_of(L.con1);
+    L.hcon1c = half_of(L.con1c);
+    L.hcon2 = half_of(L.con2);
+    L.hcon3 = half_of(L.con3);
+    L.hk = half_of(L.k);
+    L.hb = half_of(L.b);
     L.level = level;
     L.scheme = p->scheme;
     L.payoff_mask = p->payoff_mask;
@@ -280,18 +452,38 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
 
     const int q = prec->table_bits;
     const uint32_t n = 1u << q;
-    const auto& T = method1_table(q);
+    const int method = prec->rng_method > 1 ? prec->rng_method : 1;
+    // the values to tabulate: Method 1's exact interval means, or Methods 2 / 3 in FP64
+    std::vector<long double> T(n);
+    const MethodTable* mt = nullptr;
+    if (method == 1) {
+        T = method1_table(q);
+    } else {
+        mt = &method_table(q, method);
+        for (uint32_t k = 0; k < n; ++k) T[k] = mt->z[k];
+    }
     L.table_entries = n;
     if (prec->arith == MLMC_ARITH_FP32) {
         // (Z~_k, s_k): s_k is the fine step's multiplier of Z~_k, formed with the
         // same FP32 operations the kernels use on the coarse path
         out.table.resize(static_cast<size_t>(n) * 8);
         for (uint32_t k = 0; k < n; ++k) {
-            const float z = static_cast<float>(T[k]);
+            const float z = static_cast<float>(T[k]);      // one rounding (Methods 2/3: of the FP64 value)
             const float sf = mil ? multiplier32<true>(z, L.fcon1, L.fcon2, L.fcon3, 1.0f)
                                  : multiplier32<false>(z, L.fcon1, L.fcon2, L.fcon3, 1.0f);
             std::memcpy(&out.table[8 * k], &z, 4);
             std::memcpy(&out.table[8 * k + 4], &sf, 4);
+        }
+    } else if (prec->arith == MLMC_ARITH_FP16) {
+        // (Z~_k, s_k) in binary16, s_k from the same FP16 operations as the kernels
+        out.table.resize(static_cast<size_t>(n) * 4);
+        for (uint32_t k = 0; k < n; ++k) {
+            const _Float16 z = half_of(T[k]);
+            const _Float16 one = 1;
+            const _Float16 sh = mil ? multiplier_lp<true, _Float16>(z, L.hcon1, L.hcon2, L.hcon3, one)
+                                    : multiplier_lp<false, _Float16>(z, L.hcon1, L.hcon2, L.hcon3, one);
+            std::memcpy(&out.table[4 * k], &z, 2);
+            std::memcpy(&out.table[4 * k + 2], &sh, 2);
         }
     } else {
         const int* f = prec->frac_bits;
@@ -341,6 +533,13 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
             err = "the fixed-point formats saturate in the table-driven part of the step (mul1/sum1/zsq/zm1/mul3/sum2 of some table value)";
             return MLMC_E_OVERFLOW;
         }
+    }
+    // Method 2's permutation for the exact side of the correction estimator
+    if (mt && !mt->perm.empty() && estimator == MLMC_EST_CORR) {
+        const size_t off = (out.table.size() + 15) & ~size_t(15);
+        out.table.resize(off + 2 * static_cast<size_t>(n), 0);
+        std::memcpy(&out.table[off], mt->perm.data(), 2 * static_cast<size_t>(n));
+        L.perm_off = static_cast<uint32_t>(off);
     }
     L.table_bytes = static_cast<uint32_t>((out.table.size() + 15) & ~size_t(15));
     out.table.resize(L.table_bytes, 0);

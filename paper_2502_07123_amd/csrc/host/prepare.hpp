@@ -13,6 +13,15 @@ namespace mlmc {
 // Method-1 table T_q in long double (cached per q).
 const std::vector<long double>& method1_table(int q);
 
+// Table values of Methods 2 (n = 2) and 3 of Section 3 in FP64, and Method 2's
+// permutation pi (empty for Method 3); cached per (q, method).
+struct MethodTable {
+    std::vector<double> z;
+    std::vector<uint16_t> perm;
+    int iterations = 0;
+};
+const MethodTable& method_table(int q, int method);
+
 // Round T_q into the storage format of mlmc_build_table.
 mlmc_status build_table_bytes(int q, int arith, int frac_bits, void* out, std::string& err);
 

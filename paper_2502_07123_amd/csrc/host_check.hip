@@ -47,8 +47,9 @@ struct HostGroups {
                     const uint64_t g = 4 * b + w;
                     const uint64_t idx = (g & (NN - 1)) * P + ((g >> L->level) - W->path_begin);
                     Jb[idx] = wd[w];
-                    Zb[idx] = sizeof(ZT) == 4 ? static_cast<ZT>(norminv_f32(wd[w]))
-                                              : static_cast<ZT>(norminv_f64(wd[w]));
+                    const uint32_t Je = B::coupled_word(*L, tab, wd[w]);
+                    Zb[idx] = sizeof(ZT) == 4 ? static_cast<ZT>(norminv_f32(Je))
+                                              : static_cast<ZT>(norminv_f64(Je));
                 }
             }
             WorkDev W2 = *W;

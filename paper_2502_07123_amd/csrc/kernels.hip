@@ -203,12 +203,17 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
 template <bool F32>
 __global__ void __launch_bounds__(256)
 k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __restrict__ works,
-          const LevelDev* __restrict__ levels) {
+          const LevelDev* __restrict__ levels, const uint8_t* __restrict__ tables) {
     using ZT = typename std::conditional<F32, float, double>::type;
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const TileDev td = tiles[t];
         const WorkDev W = works[td.work];
-        const int lev = levels[W.lvl].level;
+        const LevelDev& L = levels[W.lvl];
+        const int lev = L.level;
+        // Method 2 couples the exact side to pi(top q bits) (the correction estimator)
+        const uint16_t* pi = L.perm_off ? reinterpret_cast<const uint16_t*>(tables + L.table_off + L.perm_off)
+                                        : nullptr;
+        const int sh = 32 - L.q;
         const uint64_t P = W.path_end - W.path_begin;
         MLMC_GLOBAL ZT* Zb = global_ptr<ZT>(W.zbuf);
         MLMC_GLOBAL uint32_t* Jb = global_ptr<uint32_t>(W.jbuf);
@@ -223,8 +228,9 @@ k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __
                 const uint64_t i = g >> lev, n = g & ((uint64_t(1) << lev) - 1);
                 const uint64_t idx = n * P + (i - W.path_begin);
                 Jb[idx] = wd[w];
-                if (F32) Zb[idx] = static_cast<ZT>(norminv_f32(wd[w]));
-                else Zb[idx] = static_cast<ZT>(norminv_f64(wd[w]));
+                const uint32_t Je = pi ? (uint32_t(pi[wd[w] >> sh]) << sh) | (wd[w] & ((1u << sh) - 1u)) : wd[w];
+                if (F32) Zb[idx] = static_cast<ZT>(norminv_f32(Je));
+                else Zb[idx] = static_cast<ZT>(norminv_f64(Je));
             }
         }
     }
@@ -322,10 +328,11 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
 }
 
 hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev* tiles,
-                          uint32_t n_tiles, const WorkDev* works, const LevelDev* levels) {
+                          uint32_t n_tiles, const WorkDev* works, const LevelDev* levels,
+                          const uint8_t* tables) {
     if (n_tiles == 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_normals<true>, dim3(grid), dim3(256), 0, st, tiles, n_tiles, works, levels);
-    else hipLaunchKernelGGL(k_normals<false>, dim3(grid), dim3(256), 0, st, tiles, n_tiles, works, levels);
+    if (f32) hipLaunchKernelGGL(k_normals<true>, dim3(grid), dim3(256), 0, st, tiles, n_tiles, works, levels, tables);
+    else hipLaunchKernelGGL(k_normals<false>, dim3(grid), dim3(256), 0, st, tiles, n_tiles, works, levels, tables);
     return hipGetLastError();
 }
 

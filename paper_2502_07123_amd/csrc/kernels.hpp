@@ -51,6 +51,11 @@ bool dispatch_variant(const Variant& v, Fn& fn) {
         case MLMC_EST_APPROX:
             if (v.arith == MLMC_ARITH_FIXED)
                 return v.fields == 1 && pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FIXED, 1>(v, fn);
+            if (v.arith == MLMC_ARITH_FP16) {
+                if (v.fields == 1) return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP16, 1>(v, fn);
+                if (v.fields == 4) return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP16, 4>(v, fn);
+                return false;
+            }
             if (v.arith != MLMC_ARITH_FP32) return false;
             switch (v.fields) {
                 case 1: return pick_mil<MLMC_EST_APPROX, MLMC_ARITH_FP32, 1>(v, fn);
@@ -63,6 +68,7 @@ bool dispatch_variant(const Variant& v, Fn& fn) {
             if (v.fields != 1) return false;
             if (v.arith == MLMC_ARITH_FIXED) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FIXED, 1>(v, fn);
             if (v.arith == MLMC_ARITH_FP32) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP32, 1>(v, fn);
+            if (v.arith == MLMC_ARITH_FP16) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP16, 1>(v, fn);
             return false;
         default:
             return false;
@@ -85,7 +91,8 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
 
 // exact normals ahead of the path kernel (FP32 for the plain-FP32 estimator, else FP64)
 hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev* tiles,
-                          uint32_t n_tiles, const WorkDev* works, const LevelDev* levels);
+                          uint32_t n_tiles, const WorkDev* works, const LevelDev* levels,
+                          const uint8_t* tables);
 
 // results[w] = fixed-order sum of work w's tile slots (one block per work)
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,

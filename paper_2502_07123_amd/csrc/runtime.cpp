@@ -410,7 +410,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         HIPCHK(launch_normals(k == 1, std::min(nn, ngrid), s,
                               reinterpret_cast<const TileDev*>(d + (k ? o_nt1 : o_nt0)), nn,
                               reinterpret_cast<const WorkDev*>(d + o_work),
-                              reinterpret_cast<const LevelDev*>(d + o_lvl)));
+                              reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab));
     }
     // path kernels, one per variant, then the fixed-order reduction of each work
     const uint32_t max_grid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * ctx->tune.blocks_per_cu;
@@ -966,6 +966,16 @@ mlmc_status mlmc_estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_proble
 mlmc_status mlmc_build_table(int32_t q, int32_t arith, int32_t frac_bits, void* out) {
     std::string err;
     return build_table_bytes(q, arith, frac_bits, out, err);
+}
+
+mlmc_status mlmc_build_rng_table(int32_t q, int32_t method, double* values, uint16_t* perm,
+                                 int32_t* iterations) {
+    if (!values || (method != 2 && method != 3) || q < 2 || q > 12 || (method == 2 && q % 2)) return MLMC_E_INVALID;
+    const MethodTable& t = method_table(q, method);
+    std::memcpy(values, t.z.data(), t.z.size() * sizeof(double));
+    if (perm && method == 2) std::memcpy(perm, t.perm.data(), t.perm.size() * sizeof(uint16_t));
+    if (iterations) *iterations = t.iterations;
+    return MLMC_OK;
 }
 
 mlmc_status mlmc_stream_words(uint64_t seed, uint32_t option_id, int32_t level, int32_t estimator,

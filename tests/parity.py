@@ -3,8 +3,8 @@
 Bars (the readings behind them are in the design notes):
 * uniform words and table indices: bit-exact;
 * fixed-point side: terminal values, payoff differences and integer sums bit-exact;
-* FP32 table side (APPROX, and the approximate side of CORR): Algorithm 1 is
-  evaluated operation by operation in FP32 on both sides -> bit-exact;
+* FP32 / FP16 table side (APPROX, and the approximate side of CORR): Algorithm 1
+  is evaluated operation by operation in that type on both sides -> bit-exact;
 * FP64 exact side: within 1e-12 of the path scale max(|X_N|, X_0), X_0 = 1 (= S0);
 * plain FP32 (own FP32 inverse normal): within the worst-case bound of
   plain32_tol(level), derived from the inverse-normal error and per-step rounding;
@@ -28,6 +28,14 @@ WIDE_FMT = {v: (w, f) for v, w, f in WIDE}
 
 EST_PLAIN, EST_APPROX, EST_CORR = 0, 1, 2
 
+# approximate normals of Section 3 beyond Method 1: (method, q, case)
+_MC = [("milstein", EST_APPROX, "fp32", False), ("euler", EST_CORR, "fp32", False),
+       ("milstein", EST_CORR, "fixed", False), ("euler", EST_APPROX, "fp16", False),
+       ("milstein", EST_APPROX, "fp32", True), ("milstein", EST_CORR, "fp16", False)]
+METHOD_CASES = ([(2, 8, c) for c in _MC] + [(3, 8, c) for c in _MC] +
+                [(2, 12, c) for c in _MC if c[2] != "fixed" and not c[3]] +
+                [(3, 11, c) for c in _MC if not c[3]])
+
 CASES = [
     # (scheme, estimator, arith, packed)
     ("euler", EST_PLAIN, "fp64", False),
@@ -43,6 +51,9 @@ CASES = [
     ("euler", EST_APPROX, "fixed", False),
     ("milstein", EST_APPROX, "fixed", False),
     ("milstein", EST_CORR, "fixed", False),
+    ("euler", EST_APPROX, "fp16", False),
+    ("milstein", EST_APPROX, "fp16", True),
+    ("milstein", EST_CORR, "fp16", False),
 ]
 
 
@@ -51,9 +62,9 @@ def case_q(case):
     return 8 if not packed else (6 if scheme == "euler" else 8)
 
 
-def oracle_run(case, level, paths, payoffs, gbm=GBM, seed=SEED, option=0):
+def oracle_run(case, level, paths, payoffs, gbm=GBM, seed=SEED, option=0, method=1, q=None):
     scheme, est, arith, packed = case
-    prec = Precision(arith if est != EST_PLAIN else "fp32", case_q(case), packed, WIDE)
+    prec = Precision(arith if est != EST_PLAIN else "fp32", q or case_q(case), packed, WIDE, method)
     return simulate(Problem(scheme, **gbm), level, paths, prec, est, seed, option, payoffs,
                     plain_arith=arith if est == EST_PLAIN else "fp64")
 
@@ -103,9 +114,9 @@ def check_close(rec, o, side, payoffs, tol, Ykey="Y", gbm=GBM):
         assert not bad.any(), (p, float(d.max()), np.flatnonzero(bad)[:5])
 
 
-def check_records(case, level, n, off, payoffs, sums, rec, o, gbm=GBM, seed=SEED):
+def check_records(case, level, n, off, payoffs, sums, rec, o, gbm=GBM, seed=SEED, q=None):
     scheme, est, arith, packed = case
-    q = case_q(case)
+    q = q or case_q(case)
     paths = np.arange(off, off + n, dtype=np.uint64)
     if not packed:
         J = philox.stream_words(seed, 0, level, est, paths * np.uint64(1 << level))

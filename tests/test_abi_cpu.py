@@ -106,7 +106,18 @@ def test_validation_rules():
     assert M.validate(p, 3, 10, 0, _ok_prec(q=13), M.EST_APPROX) == INVALID
     assert M.validate(p, 3, 10, 0, _ok_prec(packed=True), M.EST_CORR) == INVALID
     assert M.validate(p, 3, 10, 0, _ok_prec(q=5, packed=True), M.EST_APPROX) == INVALID
-    assert M.validate(p, 3, 10, 0, _ok_prec("fp16"), M.EST_APPROX) == INVALID
+    assert M.validate(p, 3, 10, 0, _ok_prec("fp16"), M.EST_APPROX) == 0
+    assert M.validate(p, 3, 10, 0, _ok_prec("fp16"), M.EST_CORR) == 0
+    assert M.validate(p, 3, 10, 0, _ok_prec("fp16", q=8, packed=True), M.EST_APPROX) == 0
+    assert M.validate(p, 3, 10, 0, _ok_prec("fp16", q=6, packed=True), M.EST_APPROX) == INVALID
+    assert M.validate(p, 3, 10, 0, _ok_prec("fp16"), M.EST_PLAIN) == INVALID
+    for method, q, ok in ((2, 8, True), (2, 7, False), (3, 7, True), (4, 8, False)):
+        pr = _ok_prec(q=q)
+        pr.rng_method = method
+        assert (M.validate(p, 3, 10, 0, pr, M.EST_CORR) == 0) == ok, (method, q)
+    pr = _ok_prec("fp32")
+    pr.rng_method = 2
+    assert M.validate(p, 3, 10, 0, pr, M.EST_PLAIN) == INVALID
     assert M.validate(p, 3, 10, 0, _ok_prec("fixed"), M.EST_PLAIN) == INVALID
     pr = _ok_prec("fixed")
     pr.frac_bits[_lib.VARS.index("mul2")] = 62                               # f_dst > f_a + f_b
@@ -142,6 +153,29 @@ def test_table_builder_equals_oracle(q):
     d = M.build_table(q, "fp64")
     ref = np.array([float(t) for t in normal.table_exact(q)])
     assert np.allclose(d, ref, rtol=1e-15, atol=1e-17)
+
+
+@pytest.mark.parametrize("q,method", [(4, 2), (8, 2), (10, 2), (12, 2), (4, 3), (8, 3), (12, 3)])
+def test_rng_method_tables_equal_oracle(q, method):
+    """Methods 2 and 3 (Section 3): values to FP64 rounding, Method 2's permutation
+    and iteration count exactly, and the same values once rounded to FP32 / FP16."""
+    from oracle import rngmethods
+    v = np.zeros(1 << q)
+    p = np.zeros(1 << q, dtype=np.uint16)
+    it = C.c_int32()
+    assert _lib.lib().mlmc_build_rng_table(q, method, v.ctypes.data_as(C.POINTER(C.c_double)),
+                                           p.ctypes.data_as(C.POINTER(C.c_uint16)), C.byref(it)) == 0
+    if method == 2:
+        z, pi = rngmethods.method2_table(q, 2)
+        assert np.array_equal(p, pi)
+        assert it.value == rngmethods.method2_lut(q, 2)[2]
+    else:
+        z = rngmethods.method3_table(q)
+    assert np.allclose(v, z, rtol=0, atol=8e-15)
+    for dt in (np.float32, np.float16):
+        assert np.array_equal(v.astype(dt), z.astype(dt))
+    bad = np.zeros(1 << 5)
+    assert _lib.lib().mlmc_build_rng_table(5, 2, bad.ctypes.data_as(C.POINTER(C.c_double)), None, None) == -1
 
 
 def test_stream_words_equal_oracle():

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import paper_2502_07123_amd as M
-from parity import (CASES, GBM, PAYS, SEED, WIDE_FMT, case_q, check_records, oracle_run)
+from parity import (CASES, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q, check_records,
+                    oracle_run)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +57,22 @@ def test_exact_normals_ahead_and_inline(ctx, case, level, ahead):
         check_records(case, level, n, off, PAYS, sums, rec, o)
     finally:
         ctx.set_tuning(**saved)
+
+
+@pytest.mark.parametrize("level", [0, 2, 5])
+@pytest.mark.parametrize("mcase", METHOD_CASES, ids=lambda m: f"m{m[0]}-q{m[1]}-" + "-".join(map(str, m[2])))
+def test_methods_2_3(ctx, mcase, level):
+    """Methods 2 and 3 of Section 3 (tables expanded by the library; Method 2's
+    permutation on the exact side of the correction estimator, in the path kernel
+    and in the normals-ahead kernel at level 5)."""
+    method, q, case = mcase
+    scheme, est, arith, packed = case
+    n, off = _n_for(level), 500 + level
+    prob = M.make_problem(scheme, PAYS, **GBM)
+    prec = M.make_precision(arith, q, packed, WIDE_FMT, method=method)
+    sums, rec = ctx.level_sums(prob, level, n, off, prec, est, SEED, debug=True)
+    o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS, method=method, q=q)
+    check_records(case, level, n, off, PAYS, sums, rec, o, q=q)
 
 
 def test_sums_without_debug_equal_debug_run(ctx):

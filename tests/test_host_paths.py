@@ -6,7 +6,8 @@ import pytest
 
 import paper_2502_07123_amd as M
 from oracle.paths import Precision, Problem, simulate
-from parity import CASES, GBM, PAYS, SEED, WIDE_FMT, case_q, check_records, oracle_run
+from parity import (CASES, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q, check_records,
+                    oracle_run)
 
 
 @pytest.mark.parametrize("level", [0, 1, 3, 6])
@@ -36,3 +37,18 @@ def test_host_narrow_fixed_counts_saturations():
     assert np.array_equal(rec["saturations"], o["sat"])
     assert sums["euro"]["saturations"] == int(o["sat"].sum())
     assert np.array_equal(rec["XN_raw"], o["XN_approx"])
+
+
+@pytest.mark.parametrize("level", [0, 3])
+@pytest.mark.parametrize("mcase", METHOD_CASES, ids=lambda m: f"m{m[0]}-q{m[1]}-" + "-".join(map(str, m[2])))
+def test_host_methods_2_3_match_oracle(mcase, level):
+    """Methods 2 and 3 of Section 3: same records as the oracle (Method 2's
+    correction estimator with the permuted coupled uniform on the exact side)."""
+    method, q, case = mcase
+    scheme, est, arith, packed = case
+    n, off = 700, 31
+    prob = M.make_problem(scheme, PAYS, **GBM)
+    prec = M.make_precision(arith, q, packed, WIDE_FMT, method=method)
+    sums, rec = M.check_paths_host(prob, level, n, off, prec, est, SEED)
+    o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS, method=method, q=q)
+    check_records(case, level, n, off, PAYS, sums, rec, o, q=q)

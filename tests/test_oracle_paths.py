@@ -166,6 +166,26 @@ def test_fixed_wide_follows_fp64_table_path(scheme):
         assert np.allclose(fixed[n]["Y"], flt[n]["Y"], atol=1e-6)
 
 
+@pytest.mark.parametrize("arith,u", [("fp32", 2.0 ** -24), ("fp16", 2.0 ** -11)])
+@pytest.mark.parametrize("scheme", ["euler", "milstein"])
+def test_float_sides_round_at_their_precision(arith, u, scheme):
+    """FP32 / FP16 table paths follow the FP64 table path within the per-step
+    rounding bound (Algorithm 1: at most ~6 roundings of unit roundoff u per step,
+    constants and table values rounded once), and deviate by at least the rounding
+    scale -- arithmetic carried out in a wider type would not."""
+    p = Problem(scheme, **GBM)
+    level, N = 4, 16
+    paths = np.arange(2000, dtype=np.uint64)
+    lo = simulate(p, level, paths, Precision(arith, 8), EST_APPROX, SEED, payoffs=("euro",))
+    ref = simulate(p, level, paths, Precision("fp64", 8), EST_APPROX, SEED, payoffs=("euro",))
+    dt = {"fp32": np.float32, "fp16": np.float16}[arith]
+    for key in ("XN_approx", "XcN_approx"):
+        assert lo[key].dtype == np.dtype(dt)
+        err = np.abs(lo[key].astype(np.float64) - ref[key]) / np.maximum(np.abs(ref[key]), 1.0)
+        assert err.max() <= 8 * N * u, (key, err.max() / u)
+        assert err.mean() >= u / 8, (key, err.mean() / u)
+
+
 def test_fixed_narrow_saturates_and_counts():
     p = Problem("euler", **GBM)
     fmt = tuple((v, w, f) if v != "X" else ("X", 8, 7) for v, w, f in WIDE)   # X < 1
