@@ -71,6 +71,39 @@ def make_items(M, prob, prec_a, prec_c, Na, Nc, offset):
     return items
 
 
+# kernel sources whose change invalidates recorded HBM counters
+KERNEL_SOURCES = ("paper_2502_07123_amd/csrc/kernels.hip", "paper_2502_07123_amd/csrc/kernels.hpp",
+                  "paper_2502_07123_amd/csrc/common.hpp", "paper_2502_07123_amd/csrc/device/paths.hpp",
+                  "paper_2502_07123_amd/csrc/device/philox.hpp", "paper_2502_07123_amd/csrc/device/norminv.hpp",
+                  "paper_2502_07123_amd/csrc/device/fixed.hpp")
+TRAFFIC_RECORD = "profiles/k_paths_approx_cfg2_hbm_traffic.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (scaled by the copy-probe factors recorded there), or None
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_RECORD)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_record: "):
+            rec = json.loads(line[len("traffic_record: "):])
+            if rec.get("source_sha256") != kernel_source_hash() or rec.get("kernel") != kernel:
+                return None
+            return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
+    return None
+
+
 def combine_np(S, scale):
     """Price estimate and its standard error from a batch's sums (R9 variances)."""
     import numpy as np
@@ -81,7 +114,7 @@ def combine_np(S, scale):
     return scale * float(m.sum()), scale * math.sqrt(float((v / n).sum()))
 
 
-def cpu_baseline(Na, Nc, budget_paths_steps=2.0e7):
+def cpu_baseline(Na, Nc, budget_paths_steps=1.5e8):
     """The oracle on a bounded sample of the same works (same levels and estimators,
     sample sizes proportional to N_l, M_l): single-threaded numpy."""
     import numpy as np
@@ -203,7 +236,10 @@ def main():
     avg_s = dom["ms"] / dom["launches"] * 1e-3
     achieved = ops / avg_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_valu() / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / peak_valu(), "traffic": None,
+                "unit": "Tlane-op/s", "frac": achieved / peak_valu(),
+                "traffic": recorded_traffic(f"k_paths<{dom['estimator']}, {dom['arith']}, "
+                                            f"{'true' if dom['scheme'] else 'false'}, {dom['payoffs']}, "
+                                            f"{'true' if dom['track'] else 'false'}, {dom['fields']}>"),
                 "kernel": {"estimator": dom["estimator"], "fields": dom["fields"],
                            "avg_launch_ms": dom["ms"] / dom["launches"],
                            "path_steps_per_launch": per_launch_steps,
