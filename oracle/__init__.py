@@ -19,6 +19,10 @@ Modules
   rngmethods  Methods 2 (sum of two small-table variables, least squares under a
               permutation, permuted coupled uniform) and 3 (piecewise linear on
               dyadic intervals) of Section 3.
+  errmodel    rounding-error model of Sections 4-6: reverse-sweep sensitivities,
+              V_indep / V_corr and their approximate-normal extension, the
+              separable cost, Lagrange widths by golden-section search and the
+              greedy integer rounding.
   mlmc        per-level sums, the nested split (Section 2.2), optimal sample
               allocation (Sections 2.1-2.2) and the adaptive driver.
 
