@@ -146,12 +146,21 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 256 MiB device-to-device (a known-size kernel that scales "
                          "the HBM byte counters of a profile)")
+    ap.add_argument("--batch", action="store_true",
+                    help="instead: the 256-option batched workload (nested vs plain FP32)")
+    ap.add_argument("--batch-eps", default="1e-2,1e-3,1e-4")
+    ap.add_argument("--serving", action="store_true",
+                    help="instead: Poisson-arrival serving, p50/p99 latency (nested vs plain FP32)")
+    ap.add_argument("--serve-rates", default="1000,5000,20000")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
+    if args.batch or args.serving:
+        return main_workloads(args)
     import numpy as np
     import torch
     import paper_2502_07123_amd as M
@@ -308,6 +317,212 @@ def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p):
     out["speedup"] = out["plain_fp32"]["seconds"] / out["nested"]["seconds"]
     out["cost_ns_per_step"] = {"plain_fp32": c_p, "approx": c_a, "corr": c_c}
     return out
+
+
+# ------------------------------------------------------- batched pricing, serving
+def draw_options(rng, n):
+    """Options of the batched / served workloads: S0, K ~ U[80,120], r ~ U[0,0.08],
+    sigma ~ U[0.1,0.5], T ~ U[0.25,2] (drawn in that order as arrays of n), payoffs
+    50% European, 30% Asian, 20% digital assigned by a permutation."""
+    import numpy as np
+    S0 = rng.uniform(80, 120, n)
+    K = rng.uniform(80, 120, n)
+    r = rng.uniform(0.0, 0.08, n)
+    sig = rng.uniform(0.1, 0.5, n)
+    T = rng.uniform(0.25, 2.0, n)
+    n_e, n_a = n // 2, int(round(0.3 * n))
+    kinds = np.array(["euro"] * n_e + ["asian"] * n_a + ["digital"] * (n - n_e - n_a))
+    kinds = kinds[rng.permutation(n)]
+    return [dict(S0=float(S0[i]), K=float(K[i]), r=float(r[i]), sigma=float(sig[i]), T=float(T[i]),
+                 kind=str(kinds[i])) for i in range(n)]
+
+
+def closed_form(o):
+    """Black-Scholes price of a European call, or of a digital call paying K; None
+    for the Asian option."""
+    from math import erf, exp, log, sqrt
+    N = lambda x: 0.5 * (1.0 + erf(x / sqrt(2.0)))
+    d1 = (log(o["S0"] / o["K"]) + (o["r"] + 0.5 * o["sigma"] ** 2) * o["T"]) / (o["sigma"] * sqrt(o["T"]))
+    d2 = d1 - o["sigma"] * sqrt(o["T"])
+    if o["kind"] == "euro":
+        return o["S0"] * N(d1) - o["K"] * exp(-o["r"] * o["T"]) * N(d2)
+    if o["kind"] == "digital":
+        return o["K"] * exp(-o["r"] * o["T"]) * N(d2)
+    return None
+
+
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def _run_cfg(M, nested, eps, costs):
+    prec = M.make_precision("fp32", Q, packed=True)
+    return M.make_run_config(eps, nested=nested, eps_units="normalised", theta=0.5, L_min=2, L_max=10,
+                             n_pilot=10_000, costs=costs, plain_arith="fp32", prec=prec)
+
+
+def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256):
+    """Poisson arrivals (exponential gaps) of pricing requests at each rate: options
+    as draw_options, eps = 10^U[-4,-2] (normalised), Milstein; nested (FP32 table +
+    FP64 correction) or plain FP32.  Latency = arrival to result: the submission's
+    lag behind the scheduled arrival plus the server's submit-to-result time.
+    Requests arriving in [warm, warm + seconds) are measured."""
+    import ctypes as C
+    import numpy as np
+    from paper_2502_07123_amd import _lib as L
+    lib = L.lib()
+    out = []
+    BUF = 512
+    tk = (C.c_uint64 * BUF)()
+    res = (L.Result * BUF)()
+    cnt = C.c_uint32()
+    for rate in rates:
+        ss = np.random.SeedSequence(1234 + int(rate))
+        g_rng, o_rng = (np.random.default_rng(x) for x in ss.spawn(2))
+        t_end = warm + seconds
+        gaps = g_rng.exponential(1.0 / rate, int(rate * t_end * 1.2) + 16)
+        arr = np.cumsum(gaps)
+        arr = arr[arr < t_end]
+        n = len(arr)
+        opts = draw_options(o_rng, n)
+        eps = 10.0 ** o_rng.uniform(-4, -2, n)
+        for mode in ("nested", "plain_fp32"):
+            nested = mode == "nested"
+            reqs = (L.Request * n)()
+            for i, o in enumerate(opts):
+                q = reqs[i]
+                q.struct_size = C.sizeof(L.Request)
+                q.option_id = i
+                q.problem = M.make_problem("milstein", (o["kind"],), S0=o["S0"], K=o["K"], r=o["r"],
+                                           sigma=o["sigma"], T=o["T"])
+                q.eps = float(eps[i])
+                q.seed = SEED
+                q.nested = 1 if nested else 0
+            ctx.set_timing(True)
+            ctx.server_start(_run_cfg(M, nested, 1e-3, costs), max_active=max_active)
+            lag = np.zeros(n)
+            lat = np.full(n, np.nan)
+            done_at = np.full(n, np.nan)
+            est = np.full(n, np.nan)
+            steps = np.zeros(n)
+            index = {}
+            t = C.c_uint64()
+            i = 0
+            t0 = time.perf_counter()
+
+            def collect():
+                while True:
+                    if lib.mlmc_poll_done(ctx.h, BUF, tk, res, C.byref(cnt)) != 0:
+                        raise RuntimeError("mlmc_poll_done failed")
+                    now = time.perf_counter() - t0
+                    for k in range(cnt.value):
+                        j = index.pop(tk[k])
+                        r = res[k]
+                        if r.status == 0:
+                            lat[j] = lag[j] + r.seconds
+                            done_at[j] = now
+                            est[j] = r.estimate
+                            steps[j] = r.path_steps
+                    if cnt.value < BUF:
+                        return
+
+            while i < n:
+                now = time.perf_counter() - t0
+                while i < n and arr[i] <= now:
+                    if lib.mlmc_submit(ctx.h, C.byref(reqs[i]), C.byref(t)) != 0:
+                        raise RuntimeError("mlmc_submit failed: " + ctx.last_error())
+                    lag[i] = now - arr[i]
+                    index[t.value] = i
+                    i += 1
+                collect()
+                if i < n:
+                    wait = arr[i] - (time.perf_counter() - t0)
+                    if wait > 2e-4:
+                        time.sleep(min(wait - 1e-4, 1e-3))
+            meas = (arr >= warm)
+            t_stop = time.perf_counter() + drain
+            while time.perf_counter() < t_stop and np.isnan(lat[meas]).any():
+                collect()
+                time.sleep(5e-4)
+            sst = ctx.server_stats()
+            wall = time.perf_counter() - t0
+            ctx.server_stop()
+            kst = ctx.kernel_stats()
+            ctx.set_timing(False)
+            ok = meas & ~np.isnan(lat)
+            span = (np.nanmax(done_at[ok]) - warm) if ok.any() else float("nan")
+            cf_err = []
+            for j in np.nonzero(ok)[0]:
+                v = closed_form(opts[j])
+                if v is not None:
+                    cf_err.append((est[j] - v) / opts[j]["S0"] / eps[j])
+            cf_err = np.asarray(cf_err)
+            out.append({
+                "rate_per_s": rate, "mode": mode, "measured": int(meas.sum()), "completed": int(ok.sum()),
+                "p50_ms": _pct(lat[ok] * 1e3, 50), "p99_ms": _pct(lat[ok] * 1e3, 99),
+                "mean_ms": float(np.mean(lat[ok]) * 1e3) if ok.any() else None,
+                "options_per_s": float(ok.sum() / span) if ok.any() else 0.0,
+                "path_steps_per_s": float(steps[ok].sum() / span) if ok.any() else 0.0,
+                "submit_lag_p99_ms": _pct(lag[meas] * 1e3, 99),
+                "closed_form_checked": int(cf_err.size),
+                "rms_err_over_eps": float(np.sqrt(np.mean(cf_err ** 2))) if cf_err.size else None,
+                "wall_s": wall, "path_kernel_busy_s": sum(k["ms"] for k in kst) * 1e-3,
+                "scheduler": {k: sst[k] for k in ("flights", "works", "plan_seconds", "land_seconds",
+                                                  "idle_seconds")},
+            })
+            print(json.dumps({"serving": out[-1]}), file=sys.stderr, flush=True)
+    return out
+
+
+def batch(M, ctx, costs, eps_list, n_opt=256):
+    """The batched workload: n_opt options (draw_options with default_rng(1234)),
+    each to RMSE eps (normalised), all options' samples of a sweep in one launch
+    sequence; nested vs plain FP32.  Wall time of mlmc_estimate_batch."""
+    import numpy as np
+    rng = np.random.default_rng(1234)
+    opts = draw_options(rng, n_opt)
+    probs = [M.make_problem("milstein", (o["kind"],), S0=o["S0"], K=o["K"], r=o["r"], sigma=o["sigma"],
+                            T=o["T"]) for o in opts]
+    out = []
+    for eps in eps_list:
+        for mode in ("nested", "plain_fp32"):
+            cfg = _run_cfg(M, mode == "nested", eps, costs)
+            t0 = time.perf_counter()
+            rs = ctx.estimate_batch(probs, cfg, SEED)
+            dt = time.perf_counter() - t0
+            errs = [(r["estimate"] - closed_form(o)) / o["S0"] / eps for r, o in zip(rs, opts)
+                    if closed_form(o) is not None]
+            ns = [sum(lv["n"][e] for lv in r["levels"] for e in range(3)) for r in rs]
+            out.append({"eps": eps, "mode": mode, "seconds": dt, "options": n_opt,
+                        "path_steps": int(sum(r["path_steps"] for r in rs)),
+                        "path_steps_per_s": sum(r["path_steps"] for r in rs) / dt,
+                        "sweeps_max": max(r["sweeps"] for r in rs), "L_max": max(r["L"] for r in rs),
+                        "samples_min": int(min(ns)), "samples_max": int(max(ns)),
+                        "closed_form_checked": len(errs),
+                        "rms_err_over_eps": float(np.sqrt(np.mean(np.square(errs))))})
+            print(json.dumps({"batch": out[-1]}), file=sys.stderr, flush=True)
+    return out
+
+
+def main_workloads(args):
+    """--batch / --serving: one JSON line with the batched and/or served workloads."""
+    import torch
+    import paper_2502_07123_amd as M
+    ctx = M.Context(0, workspace_bytes=1 << 30)
+    prob = M.make_problem("milstein", ("euro",), **GBM)
+    c_a, c_c, c_p = calibrate(M, ctx, prob, M.make_precision("fp32", Q, packed=True),
+                              M.make_precision("fp32", Q, packed=False))
+    costs = (c_p, c_a, c_c)
+    line = {"cost_ns_per_step": {"plain_fp32": c_p, "approx": c_a, "corr": c_c}}
+    if args.batch:
+        line["batch"] = batch(M, ctx, costs, [float(x) for x in args.batch_eps.split(",")])
+    if args.serving:
+        line["serving"] = serving(M, ctx, costs, [float(x) for x in args.serve_rates.split(",")],
+                                  args.serve_seconds)
+    torch.cuda.synchronize()
+    print(json.dumps(line))
+    ctx.close()
 
 
 if __name__ == "__main__":

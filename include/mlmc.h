@@ -280,16 +280,23 @@ mlmc_status mlmc_kernel_stats(mlmc_context* ctx, mlmc_kernel_stat* out, uint32_t
 /* On-line nested MLMC (Sections 2.1, 2.2 and 6): pilot samples on levels
  * 0..L_min, optimal allocation N_l = ceil(theta^-1 eps^-2 sqrt(V_l/C_l) Lambda)
  * (plain) or N~_l, N^D_l with the common Lambda (nested), sweeps of the missing
- * samples, then a bias test |mean_L| / (2^alpha - 1) > sqrt(1 - theta) eps that
- * adds level L+1 up to L_max.  Costs are the deterministic model
- * C_l = 2^l c_estimator (Section 5: C_l ~ 2^l C_RNG).  eps_units 0: eps on the
- * price / S0; 1: eps in price units. */
+ * samples, then a bias test that adds level L+1 up to L_max while
+ * max_{l = max(1, L-2)..L} |mean_l| 2^(alpha (l - L)) / (2^alpha - 1) exceeds
+ * sqrt(1 - theta) eps, with alpha = 1 (the schemes' weak order).  Nested runs choose each level's estimator once its pilot
+ * has landed: the level keeps the nested pair while
+ * (sqrt(V~ c_approx) + sqrt(V^D c_corr))^2 <= V~ c_plain (Section 6's level
+ * objective with plain samples as the full-precision alternative), otherwise its
+ * nested samples are dropped (their work still counts in path_steps) and it goes
+ * on with plain samples of plain_arith; a new level above a plain level >= 1
+ * starts plain.  Costs are the deterministic model C_l = 2^l c_estimator
+ * (Section 5: C_l ~ 2^l C_RNG).  eps_units 0: eps on the price / S0; 1: eps in
+ * price units. */
 typedef struct mlmc_run_config {
     uint32_t struct_size;
     int32_t nested;             /* 1: APPROX + CORR per level; 0: PLAIN */
     int32_t eps_units;          /* 0 normalised, 1 absolute */
     int32_t L_min, L_max;       /* 0 <= L_min <= L_max <= 20 */
-    int32_t plain_arith;        /* PLAIN generator: FP64 or FP32 */
+    int32_t plain_arith;        /* PLAIN generator (plain runs, switched levels): FP64 or FP32 */
     double eps, theta;          /* eps > 0, 0 < theta <= 1 */
     uint64_t n_pilot;           /* >= 2 */
     double cost_plain, cost_approx, cost_corr;   /* cost per fine path-step (> 0) */
@@ -331,11 +338,17 @@ mlmc_status mlmc_estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_proble
 /* ------------------------------------------------------------------ serving */
 
 /* Continuous batching.  mlmc_server_start launches a scheduler thread on the
- * context.  Requests are admitted while their device state fits in the
- * workspace (the HBM budget) and a slot is free; every sweep gathers the pending
- * work of all admitted requests into one launch, so requests that arrive while
- * others run join the next sweep.  A request's result is the same as
- * mlmc_estimate with its (seed, option_id) and run config. */
+ * context.  A request is admitted when one of max_active slots is free; its state
+ * (level sums, sample counts) stays on the host.  The scheduler keeps up to two
+ * launch sequences in flight: whenever fewer are running it gathers the next
+ * samples of every admitted request that has no work in flight (pilot, allocation
+ * top-up or a new level; Sections 2.1, 2.2 and 6) into one more sequence, so a
+ * request that arrives while others run starts in the next sequence, queued behind
+ * the running one.  Device memory is the context's workspace (the HBM budget):
+ * each sequence's plan takes a ring slice of it, older sequences land to make
+ * room, and a plan larger than the workspace runs as several sequences.  A
+ * request's result is the same as mlmc_estimate with its (seed, option_id) and run
+ * config; mlmc_result.seconds is its latency, submission to result. */
 typedef struct mlmc_server_config {
     uint32_t struct_size;
     uint32_t max_active;        /* slots: requests on the device at once (>= 1) */
@@ -357,7 +370,29 @@ mlmc_status mlmc_server_start(mlmc_context* ctx, const mlmc_server_config* cfg);
 mlmc_status mlmc_submit(mlmc_context* ctx, const mlmc_request* req, uint64_t* ticket);
 /* MLMC_PENDING until done, then MLMC_OK with the result (once).  Thread-safe. */
 mlmc_status mlmc_poll(mlmc_context* ctx, uint64_t ticket, mlmc_result* out);
-/* Finishes admitted work, stops the thread. */
+/* Up to max finished requests, oldest completion first: tickets[i] and out[i]
+ * (host arrays of max entries); *n receives the count (0 when none).  A result is
+ * handed out once, by this call or by mlmc_poll.  Thread-safe.  Errors:
+ * MLMC_E_BUSY (no server), MLMC_E_INVALID (NULL pointers). */
+mlmc_status mlmc_poll_done(mlmc_context* ctx, uint32_t max, uint64_t* tickets, mlmc_result* out,
+                           uint32_t* n);
+/* Counters of the running server since its start (host clock). */
+typedef struct mlmc_server_stats {
+    uint32_t struct_size;
+    uint32_t pad;
+    uint64_t flights;           /* launch sequences started */
+    uint64_t works;             /* (request, level, estimator) works in them */
+    uint64_t requests_done;     /* requests that converged */
+    uint64_t queued, active;    /* now: waiting for a slot / admitted */
+    double plan_seconds;        /* scheduler: next samples, planning, upload, launch */
+    double land_seconds;        /* scheduler: landing flights, adding their sums */
+    double idle_seconds;        /* scheduler: waiting for a flight or a request */
+} mlmc_server_stats;
+
+/* out->struct_size must be set.  Errors: MLMC_E_BUSY (no server), MLMC_E_VERSION. */
+mlmc_status mlmc_server_stats_get(mlmc_context* ctx, mlmc_server_stats* out);
+/* Finishes admitted requests and stops the thread; requests still queued (not
+ * admitted) end with status MLMC_E_BUSY. */
 mlmc_status mlmc_server_stop(mlmc_context* ctx);
 
 /* ------------------------------------------------- host-side helpers (no GPU) */

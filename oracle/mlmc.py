@@ -18,6 +18,19 @@ Readings:
   C_l ~ 2^l C_RNG), never live timings.
 * R13 eps is on the S0-normalised price unless eps_units = 'absolute'.
 * R5a prices are e^{-rT} S0 times the sum of level means.
+* R34 bias test: the remaining bias is estimated from the last three correction
+  levels, max over l = max(1, L-2) .. L of |mean_l| 2^(alpha (l - L)) / (2^alpha - 1)
+  (Giles' published MLMC test; a single noisy level mean stops too early), with
+  alpha = 1, the weak order of both schemes (Section 2.1), rather than a rate fitted
+  to two or three noisy level means, which can come out far too large.
+* R35 per-level estimator (nested runs): once a level's pilot has landed, the level
+  keeps the nested pair only if its cost at the optimum is below the plain
+  estimator's, (sqrt(V~ c~) + sqrt(V^D c^D))^2 <= V~ c_plain (Section 6's level
+  objective with the plain estimator as the full-precision alternative and V~ as
+  its variance); otherwise its approximate and correction samples are dropped and
+  it continues with plain samples.  A new level above a plain level l >= 1 starts
+  plain.  (Discontinuous payoffs: a table error that moves a path across the
+  jump makes V^D as large as V~, and the nested pair costs more than plain.)
 
 This module is test infrastructure: see the package docstring.
 """
@@ -141,26 +154,29 @@ class Result:
     sweeps: int = 0
 
 
-def _alpha(means):
-    """Weak rate from |mean_l| for l >= 1, floor 1/2 (default 1 with < 2 levels)."""
-    ls = [l for l in range(1, len(means)) if means[l] != 0]
-    if len(ls) < 2:
-        return 1.0
-    x = np.array(ls, float)
-    y = np.log2(np.abs([means[l] for l in ls]))
-    slope = np.polyfit(x, y, 1)[0]
-    return max(0.5, -slope)
+WEAK_ORDER = 1.0      # alpha: weak order of the Euler and Milstein schemes (Section 2.1)
+
+
+def remaining_bias(means):
+    """R34: max over l = max(1, L-2) .. L of |mean_l| 2^(alpha (l - L)) / (2^alpha - 1)
+    with alpha = WEAK_ORDER (L = 0: |mean_0| / (2^alpha - 1))."""
+    L = len(means) - 1
+    a = WEAK_ORDER
+    lo = max(1, L - 2) if L >= 1 else 0
+    return max(abs(means[l]) * 2.0 ** (a * (l - L)) for l in range(lo, L + 1)) / (2.0 ** a - 1.0)
 
 
 def estimate(prob: Problem, payoff, prec: Precision, cfg: RunConfig, seed, option=0):
     """Adaptive (nested) MLMC in the manner of Giles (2008): pilot, allocation,
-    sweeps of extra samples, then a bias test that may add a level."""
+    sweeps of extra samples, then a bias test that may add a level (R10, R34, R35)."""
     scale = math.exp(-prob.r * prob.T) * (prob.S0 if cfg.eps_units == "absolute" else 1.0)
     eps = cfg.eps / scale                      # target on the normalised sums
-    ests = (EST_APPROX, EST_CORR) if cfg.nested else (EST_PLAIN,)
+    nested = (EST_APPROX, EST_CORR)
     cost = {EST_PLAIN: cfg.cost_plain, EST_APPROX: cfg.cost_approx, EST_CORR: cfg.cost_corr}
     sums = {}
     L = cfg.L_min
+    ests = {l: nested if cfg.nested else (EST_PLAIN,) for l in range(L + 1)}
+    decided = set()
 
     def run(level, est, n):
         s = sums.setdefault((level, est), Sums())
@@ -169,42 +185,56 @@ def estimate(prob: Problem, payoff, prec: Precision, cfg: RunConfig, seed, optio
         s.add(got)
 
     for l in range(L + 1):
-        for e in ests:
+        for e in ests[l]:
             run(l, e, cfg.n_pilot)
     sweeps = 0
     while True:
         sweeps += 1
         V = {k: max(s.var(), 1e-300) for k, s in sums.items()}
-        if cfg.nested:
-            Vt = [V[(l, EST_APPROX)] for l in range(L + 1)]
-            Vd = [V[(l, EST_CORR)] for l in range(L + 1)]
-            Ct = [cost[EST_APPROX] * 2 ** l for l in range(L + 1)]
-            Cd = [cost[EST_CORR] * 2 ** l for l in range(L + 1)]
-            Nt, Nd = nested_samples(Vt, Ct, Vd, Cd, eps * eps, cfg.theta)
-            target = {(l, EST_APPROX): Nt[l] for l in range(L + 1)}
-            target.update({(l, EST_CORR): Nd[l] for l in range(L + 1)})
-        else:
-            Vp = [V[(l, EST_PLAIN)] for l in range(L + 1)]
-            Cp = [cost[EST_PLAIN] * 2 ** l for l in range(L + 1)]
-            Np = optimal_samples(Vp, Cp, eps * eps, cfg.theta)
-            target = {(l, EST_PLAIN): Np[l] for l in range(L + 1)}
-        extra = {k: int(t) - sums[k].n for k, t in target.items() if t > sums[k].n}
+        if cfg.nested:                             # R35, once per level
+            switched = False
+            for l in range(L + 1):
+                if l in decided:
+                    continue
+                decided.add(l)
+                if ests[l] != nested:
+                    continue
+                Va, Vc = V[(l, EST_APPROX)], V[(l, EST_CORR)]
+                root = math.sqrt(Va * cost[EST_APPROX]) + math.sqrt(Vc * cost[EST_CORR])
+                if root * root > Va * cost[EST_PLAIN]:
+                    ests[l] = (EST_PLAIN,)
+                    del sums[(l, EST_APPROX)], sums[(l, EST_CORR)]
+                    run(l, EST_PLAIN, cfg.n_pilot)
+                    switched = True
+            if switched:
+                continue
+        # Sections 2.1/2.2: one multiplier over every (level, estimator) in use
+        # (the formula of optimal_samples, summed in this order: level, then estimator)
+        keys = [(l, e) for l in range(L + 1) for e in ests[l]]
+        lam = 0.0
+        for (l, e) in keys:
+            lam += math.sqrt(V[(l, e)] * cost[e] * 2.0 ** l)
+        lam /= cfg.theta * eps * eps
+        Nk = [math.ceil(lam * math.sqrt(V[(l, e)] / (cost[e] * 2.0 ** l))) for (l, e) in keys]
+        extra = {k: int(t) - sums[k].n for k, t in zip(keys, Nk) if t > sums[k].n}
         if extra:
             for (l, e), dn in sorted(extra.items()):
                 run(l, e, dn)
             continue
-        means = [sum(sums[(l, e)].mean() for e in ests) for l in range(L + 1)]
-        alpha = _alpha(means)
-        bias = abs(means[L]) / (2 ** alpha - 1)
-        if bias > math.sqrt(1 - cfg.theta) * eps and L < cfg.L_max:
+        means = [sum(sums[(l, e)].mean() for e in ests[l]) for l in range(L + 1)]
+        if remaining_bias(means) > math.sqrt(1 - cfg.theta) * eps and L < cfg.L_max:
             L += 1
-            for e in ests:
+            plain_above = cfg.nested and L - 1 >= 1 and ests[L - 1] == (EST_PLAIN,)
+            ests[L] = (EST_PLAIN,) if (plain_above or not cfg.nested) else nested
+            if plain_above:
+                decided.add(L)
+            for e in ests[L]:
                 run(L, e, cfg.n_pilot)
             continue
         break
-    est = scale_price(prob) * sum(sums[(l, e)].mean() for l in range(L + 1) for e in ests)
+    est = scale_price(prob) * sum(sums[(l, e)].mean() for l in range(L + 1) for e in ests[l])
     var = scale_price(prob) ** 2 * sum(sums[(l, e)].var() / sums[(l, e)].n
-                                       for l in range(L + 1) for e in ests)
+                                       for l in range(L + 1) for e in ests[l])
     return Result(estimate=est, variance=var, L=L, sums=sums, sweeps=sweeps)
 
 

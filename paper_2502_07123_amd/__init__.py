@@ -12,7 +12,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, LEVELWORK_DTYPE, PAYOFFS, RECORD_DTYPE, SUMS_DTYPE,
-                   VARS, KernelStat, LevelWork, Tuning, MlmcError, Problem, Precision, Request, Result,
+                   VARS, KernelStat, LevelWork, ServerStats, Tuning, MlmcError, Problem, Precision, Request, Result,
                    RunConfig, ServerConfig, Sums, check, lib, make_precision, make_problem, make_run_config)
 
 __all__ = ["Context", "make_problem", "make_precision", "make_run_config", "build_table",
@@ -157,6 +157,20 @@ class Context:
             return None
         check(st, self.h)
         return r.as_dict()
+
+    def poll_done(self, max_n=1024):
+        """[(ticket, result dict)] of up to max_n finished requests, oldest first."""
+        tk = (C.c_uint64 * max_n)()
+        res = (Result * max_n)()
+        n = C.c_uint32()
+        check(lib().mlmc_poll_done(self.h, max_n, tk, res, C.byref(n)), self.h)
+        return [(tk[i], res[i].as_dict()) for i in range(n.value)]
+
+    def server_stats(self):
+        st = ServerStats()
+        st.struct_size = C.sizeof(ServerStats)
+        check(lib().mlmc_server_stats_get(self.h, C.byref(st)), self.h)
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k not in ("struct_size", "pad")}
 
     def server_stop(self):
         check(lib().mlmc_server_stop(self.h), self.h)

@@ -129,6 +129,13 @@ class ServerConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("max_active", C.c_uint32), ("run", RunConfig)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("pad", C.c_uint32), ("flights", C.c_uint64),
+                ("works", C.c_uint64), ("requests_done", C.c_uint64), ("queued", C.c_uint64),
+                ("active", C.c_uint64), ("plan_seconds", C.c_double), ("land_seconds", C.c_double),
+                ("idle_seconds", C.c_double)]
+
+
 class Request(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("option_id", C.c_uint32), ("problem", Problem),
                 ("eps", C.c_double), ("seed", C.c_uint64), ("nested", C.c_int32),
@@ -168,6 +175,8 @@ def lib():
         "mlmc_server_start": (st, [vp, P(ServerConfig)]),
         "mlmc_submit": (st, [vp, P(Request), P(u64)]),
         "mlmc_poll": (st, [vp, u64, P(Result)]),
+        "mlmc_poll_done": (st, [vp, u32, P(u64), P(Result), P(u32)]),
+        "mlmc_server_stats_get": (st, [vp, P(ServerStats)]),
         "mlmc_server_stop": (st, [vp]),
         "mlmc_build_table": (st, [i32, i32, i32, vp]),
         "mlmc_build_rng_table": (st, [i32, i32, P(C.c_double), P(C.c_uint16), P(i32)]),
@@ -191,7 +200,8 @@ EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_c
             "mlmc_level_sums_enqueue", "mlmc_level_sums_wait", "mlmc_set_timing",
             "mlmc_get_tuning", "mlmc_set_tuning",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
-            "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_server_stop",
+            "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_poll_done", "mlmc_server_stats_get",
+            "mlmc_server_stop",
             "mlmc_build_table", "mlmc_build_rng_table", "mlmc_stream_words", "mlmc_validate", "mlmc_check_paths_host",
             "mlmc_allocate")
 

@@ -408,6 +408,28 @@ static FxOp add_op(const int* f, const int* w, int fa, int fb, int d) {
     return FxOp{fm - fa, fm - fb, fm - f[d], w[d]};
 }
 
+// The table values of (q, method) rounded once to FP32 (Method 1 from its exact
+// interval means, Methods 2/3 from their FP64 values), kept for the process.
+static const std::vector<float>& table_values_f32(int q, int method) {
+    static std::map<std::pair<int, int>, std::vector<float>> cache;
+    {
+        std::lock_guard<std::mutex> lock(g_tables_mtx);
+        auto it = cache.find({q, method});
+        if (it != cache.end()) return it->second;
+    }
+    const uint32_t n = 1u << q;
+    std::vector<float> v(n);
+    if (method == 1) {
+        const auto& T = method1_table(q);
+        for (uint32_t k = 0; k < n; ++k) v[k] = static_cast<float>(T[k]);
+    } else {
+        const MethodTable& mt = method_table(q, method);
+        for (uint32_t k = 0; k < n; ++k) v[k] = static_cast<float>(mt.z[k]);
+    }
+    std::lock_guard<std::mutex> lock(g_tables_mtx);
+    return cache.emplace(std::make_pair(q, method), std::move(v)).first->second;
+}
+
 mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_precision* prec,
                           int32_t estimator, LevelPrep& out, std::string& err) {
     LevelDev& L = out.dev;
@@ -428,12 +450,14 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
     L.f2con3 = static_cast<float>(2.0 * L.con3);
     L.fk = static_cast<float>(L.k);
     L.fb = static_cast<float>(L.b);
-    L.hcon1 = half_of(L.con1);
-    L.hcon1c = half_of(L.con1c);
-    L.hcon2 = half_of(L.con2);
-    L.hcon3 = half_of(L.con3);
-    L.hk = half_of(L.k);
-    L.hb = half_of(L.b);
+    if (prec->arith == MLMC_ARITH_FP16) {
+        L.hcon1 = half_of(L.con1);
+        L.hcon1c = half_of(L.con1c);
+        L.hcon2 = half_of(L.con2);
+        L.hcon3 = half_of(L.con3);
+        L.hk = half_of(L.k);
+        L.hb = half_of(L.b);
+    }
     L.level = level;
     L.scheme = p->scheme;
     L.payoff_mask = p->payoff_mask;
@@ -453,22 +477,26 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
     const int q = prec->table_bits;
     const uint32_t n = 1u << q;
     const int method = prec->rng_method > 1 ? prec->rng_method : 1;
-    // the values to tabulate: Method 1's exact interval means, or Methods 2 / 3 in FP64
-    std::vector<long double> T(n);
-    const MethodTable* mt = nullptr;
-    if (method == 1) {
-        T = method1_table(q);
-    } else {
-        mt = &method_table(q, method);
-        for (uint32_t k = 0; k < n; ++k) T[k] = mt->z[k];
+    const MethodTable* mt = method == 1 ? nullptr : &method_table(q, method);
+    // the values to tabulate, Method 1's exact interval means or Methods 2 / 3 in FP64
+    // (the FP32 side takes them rounded once, from a per-(q, method) cache)
+    std::vector<long double> T;
+    if (prec->arith != MLMC_ARITH_FP32) {
+        if (method == 1) {
+            T = method1_table(q);
+        } else {
+            T.resize(n);
+            for (uint32_t k = 0; k < n; ++k) T[k] = mt->z[k];
+        }
     }
     L.table_entries = n;
     if (prec->arith == MLMC_ARITH_FP32) {
         // (Z~_k, s_k): s_k is the fine step's multiplier of Z~_k, formed with the
         // same FP32 operations the kernels use on the coarse path
+        const std::vector<float>& Z32 = table_values_f32(q, method);
         out.table.resize(static_cast<size_t>(n) * 8);
         for (uint32_t k = 0; k < n; ++k) {
-            const float z = static_cast<float>(T[k]);      // one rounding (Methods 2/3: of the FP64 value)
+            const float z = Z32[k];
             const float sf = mil ? multiplier32<true>(z, L.fcon1, L.fcon2, L.fcon3, 1.0f)
                                  : multiplier32<false>(z, L.fcon1, L.fcon2, L.fcon3, 1.0f);
             std::memcpy(&out.table[8 * k], &z, 4);

@@ -16,7 +16,7 @@ struct HostGroups {
     const LevelDev* L;
     const WorkDev* W;
     const void* tab;
-    bool buffered;                 // exact normals computed ahead (the runtime's default rule)
+    bool buffered;                 // exact normals computed ahead (the runtime's default rule for a workspace of 192 MiB or more)
     SlotDev out{};
     template <class Tag>
     void operator()(Tag) {

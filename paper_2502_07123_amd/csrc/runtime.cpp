@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <tuple>
+#include <unordered_map>
 
 namespace mlmc {
 
@@ -142,6 +143,7 @@ mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out)
     }
     const SlotDev* res = reinterpret_cast<const SlotDev*>(pb.p + f.down_off);
     if (out) out->assign(res, res + f.n_works);
+    if (f.sink) f.sink->assign(res, res + f.n_works);
     for (size_t i = 0; i < f.deliver.size(); ++i) {
         const mlmc_level_work& w = f.deliver[i];
         const uint32_t mask = f.masks[i];
@@ -186,33 +188,47 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     std::vector<Variant> lvl_var;
     std::vector<uint8_t> tables;
     std::map<std::string, uint32_t> lvl_index;
+    std::unordered_map<const LevelPrep*, uint32_t> lvl_of_prep;
     std::vector<WorkDev> wdev(works.size());
     if (ctx->prep_cache.size() > 4096) ctx->prep_cache.clear();
+    auto add_level = [&](const LevelPrep& lp) {
+        LevelDev L = lp.dev;
+        if (!lp.table.empty()) {
+            L.table_off = static_cast<uint32_t>(tables.size());
+            tables.insert(tables.end(), lp.table.begin(), lp.table.end());
+        }
+        levels.push_back(L);
+        lvl_var.push_back(lp.variant);
+        return static_cast<uint32_t>(levels.size() - 1);
+    };
     for (size_t i = 0; i < works.size(); ++i) {
         const WorkSpec& w = works[i];
-        const std::string key = prep_key(w.prob, w.level, w.prec, w.est);
-        auto it = lvl_index.find(key);
         uint32_t li;
-        if (it == lvl_index.end()) {
-            auto pc = ctx->prep_cache.find(key);
-            if (pc == ctx->prep_cache.end()) {
-                LevelPrep lp;
-                std::string err;
-                const mlmc_status s = prepare_level(w.prob, w.level, w.prec, w.est, lp, err);
-                if (s != MLMC_OK) return fail(ctx, s, err);
-                pc = ctx->prep_cache.emplace(key, std::move(lp)).first;
+        if (w.prep) {                       // prepared by the caller (an option's own level)
+            auto it = lvl_of_prep.find(w.prep);
+            if (it == lvl_of_prep.end()) {
+                li = add_level(*w.prep);
+                lvl_of_prep.emplace(w.prep, li);
+            } else {
+                li = it->second;
             }
-            LevelDev L = pc->second.dev;
-            if (!pc->second.table.empty()) {
-                L.table_off = static_cast<uint32_t>(tables.size());
-                tables.insert(tables.end(), pc->second.table.begin(), pc->second.table.end());
-            }
-            li = static_cast<uint32_t>(levels.size());
-            lvl_index.emplace(key, li);
-            levels.push_back(L);
-            lvl_var.push_back(pc->second.variant);
         } else {
-            li = it->second;
+            const std::string key = prep_key(w.prob, w.level, w.prec, w.est);
+            auto it = lvl_index.find(key);
+            if (it == lvl_index.end()) {
+                auto pc = ctx->prep_cache.find(key);
+                if (pc == ctx->prep_cache.end()) {
+                    LevelPrep lp;
+                    std::string err;
+                    const mlmc_status s = prepare_level(w.prob, w.level, w.prec, w.est, lp, err);
+                    if (s != MLMC_OK) return fail(ctx, s, err);
+                    pc = ctx->prep_cache.emplace(key, std::move(lp)).first;
+                }
+                li = add_level(pc->second);
+                lvl_index.emplace(key, li);
+            } else {
+                li = it->second;
+            }
         }
         WorkDev& d = wdev[i];
         std::memset(&d, 0, sizeof(d));
@@ -257,8 +273,11 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         for (uint32_t wi : g.works) {
             const WorkSpec& w = works[wi];
             const uint64_t N = uint64_t(1) << w.level;
+            // (and only while the buffer takes at most a quarter of the workspace, so a
+            // small workspace still runs every work)
             const bool zb = w.est != MLMC_EST_APPROX && w.level >= 2 && w.n <= ctx->tune.zb_max_paths &&
-                            (w.n << w.level) <= ctx->tune.zb_max_positions;
+                            (w.n << w.level) <= ctx->tune.zb_max_positions &&
+                            (w.n << w.level) * 12 <= ctx->ws_bytes / 4;
             if (zb) {
                 const bool f32 = w.est == MLMC_EST_PLAIN && w.prec->arith == MLMC_ARITH_FP32;
                 zb_f32[wi] = f32 ? 1 : 0;
@@ -464,9 +483,12 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, std
 }
 
 // ------------------------------------------------------------- adaptive MLMC
-static int n_est(const OptionRun& o) { return o.cfg.nested ? 2 : 1; }
-static int est_at(const OptionRun& o, int i) {
-    return o.cfg.nested ? (i == 0 ? MLMC_EST_APPROX : MLMC_EST_CORR) : MLMC_EST_PLAIN;
+// estimators a level uses: the nested pair, or plain (plain runs; levels switched
+// by the per-level choice below)
+static bool level_plain(const OptionRun& o, int l) { return !o.cfg.nested || o.plain_lv[l]; }
+static int n_est(const OptionRun& o, int l) { return level_plain(o, l) ? 1 : 2; }
+static int est_at(const OptionRun& o, int l, int i) {
+    return level_plain(o, l) ? MLMC_EST_PLAIN : (i == 0 ? MLMC_EST_APPROX : MLMC_EST_CORR);
 }
 static double s_mean(const SlotDev& s) { return s.n ? s.s1[0] / static_cast<double>(s.n) : 0.0; }
 static double s_var(const SlotDev& s) {
@@ -483,6 +505,8 @@ void option_init(OptionRun& o) {
     o.saturations = 0;
     o.sums.assign(static_cast<size_t>(o.cfg.L_max) + 1, std::array<SlotDev, 3>{});
     for (auto& a : o.sums) for (auto& s : a) std::memset(&s, 0, sizeof(s));
+    o.plain_lv.assign(static_cast<size_t>(o.cfg.L_max) + 1, 0);
+    o.decided.assign(static_cast<size_t>(o.cfg.L_max) + 1, 0);
     o.t_start = now_seconds();
 }
 
@@ -496,42 +520,60 @@ static double est_cost(const OptionRun& o, int est) {
                                  : (est == MLMC_EST_APPROX ? o.cfg.cost_approx : o.cfg.cost_corr);
 }
 
-static double weak_alpha(const std::vector<double>& m) {
-    // least-squares slope of log2 |mean_l| over l >= 1; floor 1/2; 1 if < 2 points
-    std::vector<double> x, y;
-    for (size_t l = 1; l < m.size(); ++l)
-        if (m[l] != 0.0) { x.push_back(double(l)); y.push_back(std::log2(std::fabs(m[l]))); }
-    if (x.size() < 2) return 1.0;
-    double sx = 0, sy = 0, sxx = 0, sxy = 0;
-    const double n = double(x.size());
-    for (size_t i = 0; i < x.size(); ++i) { sx += x[i]; sy += y[i]; sxx += x[i] * x[i]; sxy += x[i] * y[i]; }
-    const double slope = (n * sxy - sx * sy) / (n * sxx - sx * sx);
-    return std::max(0.5, -slope);
+// Remaining bias after level L (R34, Giles' MLMC test): the last three correction
+// levels, max over l = max(1, L-2) .. L of |mean_l| 2^(alpha (l - L)), over
+// 2^alpha - 1, with alpha = 1, the weak order of both schemes (Section 2.1).
+static double remaining_bias(const std::vector<double>& m) {
+    constexpr double alpha = 1.0;
+    const int L = static_cast<int>(m.size()) - 1;
+    const int lo = L >= 1 ? std::max(1, L - 2) : 0;
+    double r = 0.0;
+    for (int l = lo; l <= L; ++l) r = std::max(r, std::fabs(m[l]) * std::pow(2.0, alpha * (l - L)));
+    return r / (std::pow(2.0, alpha) - 1.0);
 }
 
 std::vector<Pending> option_advance(OptionRun& o) {
     std::vector<Pending> pend;
     if (o.done) return pend;
-    const int ne = n_est(o);
     for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < ne; ++i) {
-            const uint64_t have = o.sums[l][est_at(o, i)].n;
-            if (have < o.cfg.n_pilot) pend.push_back({l, est_at(o, i), o.cfg.n_pilot - have});
+        for (int i = 0; i < n_est(o, l); ++i) {
+            const int e = est_at(o, l, i);
+            const uint64_t have = o.sums[l][e].n;
+            if (have < o.cfg.n_pilot) pend.push_back({l, e, o.cfg.n_pilot - have});
         }
     if (!pend.empty()) return pend;
+    // per-level estimator (R35, once per level after its pilot): the nested pair only
+    // while it is cheaper than plain samples, (sqrt(V~ c~) + sqrt(V^D c^D))^2 <= V~ c
+    if (o.cfg.nested) {
+        for (int l = 0; l <= o.L; ++l) {
+            if (o.decided[l]) continue;
+            o.decided[l] = 1;
+            if (o.plain_lv[l]) continue;
+            const double Va = std::max(s_var(o.sums[l][MLMC_EST_APPROX]), 1e-300);
+            const double Vc = std::max(s_var(o.sums[l][MLMC_EST_CORR]), 1e-300);
+            const double root = std::sqrt(Va * o.cfg.cost_approx) + std::sqrt(Vc * o.cfg.cost_corr);
+            if (root * root > Va * o.cfg.cost_plain) {
+                o.plain_lv[l] = 1;
+                std::memset(&o.sums[l][MLMC_EST_APPROX], 0, sizeof(SlotDev));
+                std::memset(&o.sums[l][MLMC_EST_CORR], 0, sizeof(SlotDev));
+                pend.push_back({l, MLMC_EST_PLAIN, o.cfg.n_pilot});
+            }
+        }
+        if (!pend.empty()) return pend;
+    }
     const double eps = eps_internal(o);
     // optimal allocation over all (level, estimator) pairs with one multiplier
     double lam = 0.0;
     for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < ne; ++i) {
-            const int e = est_at(o, i);
+        for (int i = 0; i < n_est(o, l); ++i) {
+            const int e = est_at(o, l, i);
             const double V = std::max(s_var(o.sums[l][e]), 1e-300);
             lam += std::sqrt(V * est_cost(o, e) * std::ldexp(1.0, l));
         }
     lam /= o.cfg.theta * eps * eps;
     for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < ne; ++i) {
-            const int e = est_at(o, i);
+        for (int i = 0; i < n_est(o, l); ++i) {
+            const int e = est_at(o, l, i);
             const double V = std::max(s_var(o.sums[l][e]), 1e-300);
             const double target = std::ceil(lam * std::sqrt(V / (est_cost(o, e) * std::ldexp(1.0, l))));
             const uint64_t t = target > 1.8e19 ? UINT64_MAX : static_cast<uint64_t>(target);
@@ -540,12 +582,15 @@ std::vector<Pending> option_advance(OptionRun& o) {
     if (!pend.empty()) return pend;
     std::vector<double> means(o.L + 1, 0.0);
     for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < ne; ++i) means[l] += s_mean(o.sums[l][est_at(o, i)]);
-    const double alpha = weak_alpha(means);
-    const double bias = std::fabs(means[o.L]) / (std::pow(2.0, alpha) - 1.0);
-    if (bias > std::sqrt(1.0 - o.cfg.theta) * eps && o.L < o.cfg.L_max) {
+        for (int i = 0; i < n_est(o, l); ++i) means[l] += s_mean(o.sums[l][est_at(o, l, i)]);
+    if (remaining_bias(means) > std::sqrt(1.0 - o.cfg.theta) * eps && o.L < o.cfg.L_max) {
         o.L += 1;
-        for (int i = 0; i < ne; ++i) pend.push_back({o.L, est_at(o, i), o.cfg.n_pilot});
+        // a new level above a plain level l >= 1 starts plain
+        if (o.cfg.nested && o.L - 1 >= 1 && o.plain_lv[o.L - 1]) {
+            o.plain_lv[o.L] = 1;
+            o.decided[o.L] = 1;
+        }
+        for (int i = 0; i < n_est(o, o.L); ++i) pend.push_back({o.L, est_at(o, o.L, i), o.cfg.n_pilot});
         return pend;
     }
     o.done = true;
@@ -621,6 +666,20 @@ static mlmc_status run_works_split(mlmc_context* ctx, const std::vector<WorkSpec
     return MLMC_OK;
 }
 
+mlmc_status option_prep(OptionRun& o, int level, int est, const mlmc_precision* prec,
+                        const LevelPrep*& out, std::string& err) {
+    if (o.preps.size() <= static_cast<size_t>(level)) o.preps.resize(static_cast<size_t>(level) + 1);
+    std::shared_ptr<const LevelPrep>& slot = o.preps[level][est];
+    if (!slot) {
+        auto lp = std::make_shared<LevelPrep>();
+        const mlmc_status s = prepare_level(&o.prob, level, prec, est, *lp, err);
+        if (s != MLMC_OK) return s;
+        slot = std::move(lp);
+    }
+    out = slot.get();
+    return MLMC_OK;
+}
+
 mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, bool& ran) {
     ran = false;
     std::vector<mlmc_precision> plain(opts.size());
@@ -641,6 +700,9 @@ mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, b
             w.path_begin = o.sums[p.level][p.est].n;
             w.n = p.n;
             w.debug = 0;
+            std::string err;
+            const mlmc_status ps = option_prep(o, p.level, p.est, w.prec, w.prep, err);
+            if (ps != MLMC_OK) return fail(ctx, ps, err);
             works.push_back(w);
             who.emplace_back(i, p);
         }
@@ -692,7 +754,9 @@ mlmc_status validate_run(const mlmc_problem* prob, const mlmc_run_config* cfg, s
             c.packed = 0;
             if ((s = validate_precision(&c, MLMC_EST_CORR, prob, err)) != MLMC_OK) return s;
         }
-    } else if (cfg->plain_arith != MLMC_ARITH_FP64 && cfg->plain_arith != MLMC_ARITH_FP32) {
+    }
+    // plain samples: plain runs, and nested levels switched to plain
+    if (cfg->plain_arith != MLMC_ARITH_FP64 && cfg->plain_arith != MLMC_ARITH_FP32) {
         err = "plain_arith must be FP64 or FP32";
         return MLMC_E_INVALID;
     }

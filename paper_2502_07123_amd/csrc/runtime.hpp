@@ -45,6 +45,7 @@ struct WorkSpec {
     uint32_t option;
     uint64_t path_begin, n;
     uint64_t debug;                 // device address of records or 0
+    const LevelPrep* prep = nullptr;   // the level prepared by the caller, or null
 };
 
 struct Server;
@@ -73,6 +74,7 @@ struct Flight {
     std::vector<Timed> timed;
     std::vector<mlmc_level_work> deliver;   // enqueued batches: where results go
     std::vector<uint32_t> masks;            // their payoff masks
+    std::shared_ptr<std::vector<SlotDev>> sink;   // server flights: per-work results
 };
 
 }  // namespace mlmc
@@ -142,6 +144,10 @@ struct OptionRun {
     uint64_t path_steps = 0;
     uint64_t saturations = 0;
     std::vector<std::array<SlotDev, 3>> sums;   // host copy per level, estimator
+    std::vector<uint8_t> plain_lv;              // nested runs: level switched to plain
+    std::vector<uint8_t> decided;               // nested runs: level's estimator chosen
+    // levels prepared for this option (constants, table, variant), per estimator
+    std::vector<std::array<std::shared_ptr<const LevelPrep>, 3>> preps;
 };
 
 void option_init(OptionRun& o);
@@ -151,6 +157,9 @@ struct Pending {
     uint64_t n;
 };
 std::vector<Pending> option_advance(OptionRun& o);
+// The option's prepared level (built once per (level, estimator) and kept).
+mlmc_status option_prep(OptionRun& o, int level, int est, const mlmc_precision* prec,
+                        const LevelPrep*& out, std::string& err);
 void option_result(const OptionRun& o, mlmc_result& r);
 mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts);
 // One sweep over the options that are not done (ran: whether any work was run).

@@ -94,42 +94,52 @@ def test_ticket_errors(ctx):
 
 # ------------------------------------------------------------------ estimates
 DRIVER_CASES = [
-    # (nested, scheme, arith of the low-precision side / plain arithmetic)
-    (False, "euler", "fp64"),
-    (False, "milstein", "fp32"),
-    (True, "milstein", "fp32"),
-    (True, "euler", "fixed"),
+    # (nested, scheme, arith of the low-precision side / plain arithmetic, payoff)
+    (False, "euler", "fp64", "euro"),
+    (False, "milstein", "fp32", "euro"),
+    (True, "milstein", "fp32", "euro"),
+    (True, "euler", "fixed", "euro"),
+    # levels >= 1 switch to plain FP64 samples (the table moves paths across the jump)
+    (True, "milstein", "fp32", "digital"),
 ]
 
 
-def _configs(nested, scheme, arith, eps=0.001):
+def _configs(nested, scheme, arith, eps=0.001, payoff="euro"):
     kw = dict(eps=eps, theta=0.5, L_min=2, L_max=6, n_pilot=2000)
     costs = (1.0, 0.1, 1.1)
     plain = arith if not nested else "fp32"
-    prec = M.make_precision(arith if nested else "fp32", 8, False, WIDE_FMT if arith == "fixed" else None)
+    q = 8
+    if payoff == "digital":
+        kw.update(eps=0.003, n_pilot=10_000)
+        costs, plain, q = (1.0, 0.5, 2.9), "fp64", 6
+    prec = M.make_precision(arith if nested else "fp32", q, False, WIDE_FMT if arith == "fixed" else None)
     cfg = M.make_run_config(nested=nested, plain_arith=plain, prec=prec, costs=costs, **kw)
     ocfg = om.RunConfig(nested=nested, plain_arith=plain, cost_plain=costs[0], cost_approx=costs[1],
                         cost_corr=costs[2], **kw)
-    oprec = OPrecision(arith if nested else "fp32", 8, False, WIDE if arith == "fixed" else ())
+    oprec = OPrecision(arith if nested else "fp32", q, False, WIDE if arith == "fixed" else ())
     return cfg, ocfg, oprec
 
 
 @pytest.mark.parametrize("case", DRIVER_CASES, ids=lambda c: "-".join(map(str, c)))
 def test_estimate_follows_the_oracle_driver(ctx, case):
-    nested, scheme, arith = case
-    cfg, ocfg, oprec = _configs(nested, scheme, arith)
-    r = ctx.estimate(M.make_problem(scheme, ("euro",), **EURO), cfg, SEED, option=3)
-    o = om.estimate(OProblem(scheme, **EURO), "euro", oprec, ocfg, SEED, option=3)
+    """Same levels, same estimator per level (R35), same sample counts; estimate and
+    variance within the summation-order bound."""
+    nested, scheme, arith, payoff = case
+    cfg, ocfg, oprec = _configs(nested, scheme, arith, payoff=payoff)
+    r = ctx.estimate(M.make_problem(scheme, (payoff,), **EURO), cfg, SEED, option=3)
+    o = om.estimate(OProblem(scheme, **EURO), payoff, oprec, ocfg, SEED, option=3)
     assert r["status"] == 0
     assert r["L"] == o.L
-    ests = (M.EST_APPROX, M.EST_CORR) if nested else (M.EST_PLAIN,)
+    if payoff == "digital":                 # the per-level switch happened
+        assert (1, M.EST_PLAIN) in o.sums and (0, M.EST_APPROX) in o.sums
     # plain FP32 uses its own FP32 inverse normal: its sums differ from the oracle's
     # by ~1e-7 relative, so an allocation may round one sample differently
     slack = 1 if (not nested and arith == "fp32") else 0
     same_n = True
     for l in range(o.L + 1):
-        for e in ests:
-            d = abs(r["levels"][l]["n"][e] - o.sums[(l, e)].n)
+        for e in (M.EST_PLAIN, M.EST_APPROX, M.EST_CORR):
+            want = o.sums[(l, e)].n if (l, e) in o.sums else 0
+            d = abs(r["levels"][l]["n"][e] - want)
             assert d <= slack, (l, e)
             same_n = same_n and d == 0
     if not slack:
@@ -156,27 +166,94 @@ def test_batched_estimates_equal_each_alone(ctx):
             assert batch[i][k] == alone[k], (i, k)
 
 
-@pytest.mark.parametrize("max_active", [1, 64])
-def test_server_results_equal_each_alone(ctx, max_active):
-    cfg, _, _ = _configs(True, "milstein", "fp32", eps=0.003)
-    probs = _strikes()
-    alone = [ctx.estimate(p, cfg, SEED + 7, option=10 + i) for i, p in enumerate(probs)]
-    ctx.server_start(cfg, max_active=max_active)
+def _collect(ctx, tickets, timeout=60.0):
+    import time
+    got = {}
+    t_end = time.time() + timeout
+    while len(got) < len(tickets) and time.time() < t_end:
+        for t, r in ctx.poll_done(64):
+            got[t] = r
+        time.sleep(0.0005)
+    return got
+
+
+def _mix():
+    """(problem, eps, nested) of six requests: three strikes, nested and plain FP32."""
+    out = []
+    for i, p in enumerate(_strikes()):
+        out.append((p, 0.003, True))
+        out.append((p, 0.004 + 0.001 * i, False))
+    return out
+
+
+@pytest.mark.parametrize("max_active,ws", [(1, 512 << 20), (64, 512 << 20), (4, 1 << 20)],
+                         ids=["1-slot", "64-slots", "4-slots-1MiB"])
+def test_server_results_equal_each_alone(ctx, max_active, ws):
+    """Requests submitted in two waves (the second while the first run) with mixed
+    eps and estimators: each result equals mlmc_estimate of the same request alone,
+    also with one slot and with a 1 MiB workspace (plans of several launch
+    sequences)."""
+    import time
+    c = ctx if ws == (512 << 20) else M.Context(0, workspace_bytes=ws)
     try:
-        tickets = [ctx.submit(p, 0.003, SEED + 7, option=10 + i) for i, p in enumerate(probs)]
-        got = {}
-        import time
-        t_end = time.time() + 60
-        while len(got) < len(tickets) and time.time() < t_end:
-            for t in tickets:
-                if t not in got:
-                    r = ctx.poll(t)
-                    if r is not None:
-                        got[t] = r
-            time.sleep(0.001)
-        assert len(got) == len(tickets)
+        cfg, _, _ = _configs(True, "milstein", "fp32", eps=0.003)
+        reqs = _mix()
+        alone = []
+        for i, (p, eps, nested) in enumerate(reqs):
+            cfg.eps, cfg.nested = eps, 1 if nested else 0
+            alone.append(c.estimate(p, cfg, SEED + 7, option=10 + i))
+        cfg.eps, cfg.nested = 0.003, 1
+        c.server_start(cfg, max_active=max_active)
+        try:
+            tickets = [c.submit(p, eps, SEED + 7, option=10 + i, nested=nested)
+                       for i, (p, eps, nested) in enumerate(reqs[:2])]
+            time.sleep(0.002)
+            tickets += [c.submit(p, eps, SEED + 7, option=12 + i, nested=nested)
+                        for i, (p, eps, nested) in enumerate(reqs[2:])]
+            got = _collect(c, tickets)
+            assert len(got) == len(tickets)
+        finally:
+            c.server_stop()
+        for t, a in zip(tickets, alone):
+            assert got[t]["status"] == 0
+            assert got[t]["seconds"] > 0
+            for k in ("estimate", "variance", "L", "levels", "path_steps"):
+                assert got[t][k] == a[k], k
+    finally:
+        if c is not ctx:
+            c.close()
+
+
+def test_server_poll_and_stop(ctx):
+    """mlmc_poll and mlmc_poll_done hand each result out once; stopping cancels the
+    requests not yet admitted and finishes the admitted one."""
+    cfg, _, _ = _configs(True, "milstein", "fp32", eps=0.003)
+    p = _strikes()[1]
+    ctx.server_start(cfg, max_active=1)
+    try:
+        t0 = ctx.submit(p, 0.003, SEED, option=1)
+        queued = [ctx.submit(p, 0.003, SEED, option=2 + i) for i in range(3)]
     finally:
         ctx.server_stop()
-    for t, a in zip(tickets, alone):
-        for k in ("estimate", "variance", "L", "levels", "path_steps"):
-            assert got[t][k] == a[k], k
+    with pytest.raises(M.MlmcError):
+        ctx.poll(t0)                        # no server any more
+    ctx.server_start(cfg, max_active=2)
+    try:
+        t1 = ctx.submit(p, 0.003, SEED, option=1)
+        got = _collect(ctx, [t1])
+        assert list(got) == [t1] and got[t1]["status"] == 0
+        assert ctx.poll_done(8) == []
+        with pytest.raises(M.MlmcError):
+            ctx.poll(t1)                    # already handed out
+        t2 = ctx.submit(p, 0.003, SEED, option=1)
+        r = None
+        for _ in range(60000):
+            r = ctx.poll(t2)
+            if r is not None:
+                break
+            import time
+            time.sleep(0.001)
+        assert r is not None and r["estimate"] == got[t1]["estimate"]
+        assert ctx.poll_done(8) == []       # taken by mlmc_poll
+    finally:
+        ctx.server_stop()

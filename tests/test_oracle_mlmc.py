@@ -104,3 +104,44 @@ def test_adaptive_nested_matches_plain(adaptive_results):
     # the correction estimator's variance is far below the approximate one's (Section 2.2)
     for l in range(nested.L + 1):
         assert nested.sums[(l, 2)].var() < 0.2 * nested.sums[(l, 1)].var()
+
+
+def test_remaining_bias_uses_three_levels():
+    """R34 with alpha = 1: a level mean that is small by chance does not hide the
+    bias that the two levels below it show; with geometric means every term of the
+    max agrees."""
+    from oracle.mlmc import remaining_bias
+    assert remaining_bias([1.0, 0.08, 0.04, 0.02, 0.01]) == 0.01
+    assert remaining_bias([1.0, 0.08, 0.04, 0.02, 1e-6]) == 0.01          # 0.02 / 2
+    assert remaining_bias([1.0, 0.08, 0.04, -1e-6, 1e-6]) == 0.01         # 0.04 / 4
+    assert remaining_bias([1.0, 0.5, 1e-6]) == 0.25                     # level 0 excluded
+    assert remaining_bias([0.3]) == 0.3
+    assert remaining_bias([0.3, -0.05]) == 0.05
+
+
+def digital_closed_form(S0, K, r, sigma, T):
+    """A digital call paying K: K e^{-rT} N(d2)."""
+    d2 = (math.log(S0 / K) + (r - 0.5 * sigma ** 2) * T) / (sigma * math.sqrt(T))
+    return K * math.exp(-r * T) * 0.5 * (1 + math.erf(d2 / math.sqrt(2)))
+
+
+def test_discontinuous_payoff_switches_levels_to_plain():
+    """R35: for a digital call the table error moves paths across the jump, the
+    correction variance is as large as the approximate one from level 1 on, and
+    those levels continue with plain samples (level 0 keeps the nested pair); the
+    price stays within the error budget of the closed form.  A European call keeps
+    the nested pair on every level."""
+    p = Problem("milstein", **GBM)
+    cfg = RunConfig(eps=3e-3, eps_units="normalised", theta=0.5, L_min=2, L_max=6,
+                    n_pilot=10_000, nested=True, plain_arith="fp64",
+                    cost_plain=1.0, cost_approx=0.5, cost_corr=2.9)
+    r = estimate(p, "digital", Precision("fp32", 6), cfg, seed=1234)
+    assert (0, 1) in r.sums and (0, 2) in r.sums and (0, 0) not in r.sums
+    for l in range(1, r.L + 1):
+        assert (l, 0) in r.sums and (l, 1) not in r.sums and (l, 2) not in r.sums, l
+    ref = digital_closed_form(p.S0, p.K, p.r, p.sigma, p.T)
+    eps_price = cfg.eps * p.S0
+    assert r.variance <= cfg.theta * eps_price ** 2 * 1.01
+    assert abs(r.estimate - ref) < 4 * math.sqrt(r.variance) + eps_price
+    e = estimate(p, "euro", Precision("fp32", 6), cfg, seed=1234)
+    assert all((l, 1) in e.sums and (l, 2) in e.sums and (l, 0) not in e.sums for l in range(e.L + 1))
