@@ -395,6 +395,74 @@ mlmc_status mlmc_server_stats_get(mlmc_context* ctx, mlmc_server_stats* out);
  * admitted) end with status MLMC_E_BUSY. */
 mlmc_status mlmc_server_stop(mlmc_context* ctx);
 
+/* ------------------------------------------- rounding-error model (Sections 4-6) */
+
+/* The linear error model of one level of the European call (Section 4.2).
+ * For variable v (MLMC_V_*) with instances j (one per fine and per coarse step of a
+ * sample, Z one per fine normal, con1 twice: con1 and con1c):
+ *   S[v] = sum_j E[xbar_vj^2],  R[v] = sum_j sqrt(E[xbar_vj^2]),
+ * xbar the sensitivity d(dP)/dx of the level sample dP = P(X_N) - P(Xc_{N/2}) (level
+ * 0: P(X_1)), on FP64 paths with exact normals of the correction estimator's stream.
+ * e[v]: the exponent with |x| < 2^e over every instance (Section 4.1); Z's from the
+ * q-bit Method-1 table.  V_indep(d) = (1/12) sum_v S[v] 4^(e[v] - d[v]) and
+ * V_corr(d) = (sum_v R[v] 2^(e[v] - d[v] - 1))^2; with approximate normals
+ * (Section 4.3) the terms S[Z] mse and R[Z] sqrt(mse) are added (without the 1/12:
+ * the table's error is not a uniform rounding error).  used[v] = 0: the variable is
+ * not in the scheme (Euler: con3, zsq, zm1, mul3, sum2). */
+typedef struct mlmc_error_model {
+    uint32_t struct_size;
+    int32_t level, scheme, table_bits;
+    uint64_t n_paths;
+    int32_t used[MLMC_NVARS];
+    int32_t e[MLMC_NVARS];
+    double S[MLMC_NVARS];
+    double R[MLMC_NVARS];
+    double V_level;             /* V[dP] of the exact paths (normalised units) */
+    double mse;                 /* Method-1 table MSE at table_bits */
+} mlmc_error_model;
+
+/* Runs the sensitivity kernel over paths 0 .. n_paths-1 of (seed, option_id) at
+ * `level` (one wave of 64 paths per lane group, FP64 atomics into the workspace,
+ * which it needs whole: in-flight batches are landed first).  prob: one payoff,
+ * the European call; q: the table whose MSE and largest value enter the model.
+ * out->struct_size must be set.  Errors: MLMC_E_INVALID (payoff, level > 20,
+ * n_paths < 2, q outside 1..16), MLMC_E_NOMEM (workspace below 12 (3/2) 2^level
+ * doubles), MLMC_E_DEVICE. */
+mlmc_status mlmc_error_model_compute(mlmc_context* ctx, const mlmc_problem* prob, int32_t level,
+                                     uint64_t n_paths, int32_t q, uint64_t seed, uint32_t option_id,
+                                     mlmc_error_model* out);
+
+/* Bit widths of one level (Section 6).  Cost: the separable relaxation of Section 5,
+ * C(d) = sum_v (1/2) M_v d_v^2 + M'_v d_v with M (M') the multiplications
+ * (additions) that take v as an operand per sample, counted on the kernel's
+ * operations (fine step: the table's multiplier times X, and the add; coarse step:
+ * the whole chain).  For a multiplier lambda each d_v solves
+ * ln4 (S_v / 12) 4^(e_v - d_v) = lambda (M_v d_v + M'_v) on [0, d_max] (d_max = 31,
+ * Z 30), lambda minimises the level objective sqrt(V_level C(d)) +
+ * sqrt(V^D(d) C_l), C_l = 2^level c_rng, V^D = V_indep (+ the table term when
+ * rng_term) by golden-section search over the lambdas of uniform widths 4..16, and
+ * d is rounded by the greedy ratio rule (floor, then one bit at a time in order of
+ * variance gained per cost until V^D <= V^D(real d)).  word_bits / frac_bits: the
+ * kernel's formats of d_int (w = d + 1, f = d - e), with fractional bits that
+ * could not change a result dropped (a product keeps at most f_a + f_b, a sum at
+ * most max(f_a, f_b), summands differ by at most 30, zsq keeps at most 30), so
+ * they pass mlmc_validate.  Host only.  Errors: MLMC_E_INVALID, MLMC_E_VERSION. */
+typedef struct mlmc_width_plan {
+    uint32_t struct_size;
+    int32_t best_uniform;       /* the uniform width of 4..16 with the least objective */
+    double lambda;
+    double objective;           /* at the real widths */
+    double objective_uniform;   /* at best_uniform */
+    double v_indep, cost;       /* at d_int */
+    double d_real[MLMC_NVARS];
+    int32_t d_int[MLMC_NVARS];
+    int32_t word_bits[MLMC_NVARS];
+    int32_t frac_bits[MLMC_NVARS];
+} mlmc_width_plan;
+
+mlmc_status mlmc_optimise_widths(const mlmc_error_model* model, double c_rng, int32_t rng_term,
+                                 mlmc_width_plan* out);
+
 /* ------------------------------------------------- host-side helpers (no GPU) */
 
 /* Method-1 table (Section 3.1): T_q[k] = 2^q (phi(Phi^-1(k 2^-q)) -

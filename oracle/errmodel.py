@@ -383,13 +383,14 @@ def kernel_formats(m: Model, d, scheme):
     rounding error: a result never keeps more fractional bits than its exact value
     has (product f_a + f_b, sum max(f_a, f_b)), two summands differ by at most 30
     fractional bits, zsq keeps at most 30, and words fit 32 bits (Z 31) -- a
-    fractional bit above these limits rounds nothing.  w follows f: w = f + e + 1."""
+    fractional bit above these limits rounds nothing; f is at least 0.  w follows f:
+    w = f + e + 1."""
     F = {v: [w, f] for v, (w, f) in formats(m, d).items()}
     e = {v: int(m.e[IX[v]]) for v in F}
     mil = scheme == "milstein"
 
     def cap(v):
-        F[v][1] = min(F[v][1], (30 if v == "Z" else 31) - e[v])
+        F[v][1] = max(min(F[v][1], (30 if v == "Z" else 31) - e[v]), 0)
         F[v][0] = F[v][1] + e[v] + 1
 
     def prod(dst, a, b):

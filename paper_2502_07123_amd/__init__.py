@@ -12,11 +12,12 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, LEVELWORK_DTYPE, PAYOFFS, RECORD_DTYPE, SUMS_DTYPE,
-                   VARS, KernelStat, LevelWork, ServerStats, Tuning, MlmcError, Problem, Precision, Request, Result,
-                   RunConfig, ServerConfig, Sums, check, lib, make_precision, make_problem, make_run_config)
+                   VARS, ErrorModel, KernelStat, LevelWork, MlmcError, Precision, Problem, Request, Result,
+                   RunConfig, ServerConfig, ServerStats, Sums, Tuning, WidthPlan, check, error_model_struct, lib,
+                   make_precision, make_problem, make_run_config)
 
 __all__ = ["Context", "make_problem", "make_precision", "make_run_config", "build_table",
-           "stream_words", "check_paths_host", "allocate", "validate", "MlmcError",
+           "stream_words", "check_paths_host", "allocate", "validate", "optimise_widths", "MlmcError",
            "EST_PLAIN", "EST_APPROX", "EST_CORR", "PAYOFFS", "VARS", "RECORD_DTYPE", "SUMS_DTYPE",
            "SumsBatch"]
 
@@ -166,6 +167,14 @@ class Context:
         check(lib().mlmc_poll_done(self.h, max_n, tk, res, C.byref(n)), self.h)
         return [(tk[i], res[i].as_dict()) for i in range(n.value)]
 
+    # ---- rounding-error model and bit widths (Sections 4-6)
+    def error_model(self, problem, level, n_paths, q, seed, option=0):
+        m = ErrorModel()
+        m.struct_size = C.sizeof(ErrorModel)
+        check(lib().mlmc_error_model_compute(self.h, C.byref(problem), level, int(n_paths), q, int(seed),
+                                             option, C.byref(m)), self.h)
+        return m.as_dict()
+
     def server_stats(self):
         st = ServerStats()
         st.struct_size = C.sizeof(ServerStats)
@@ -242,6 +251,16 @@ class SumsBatch:
 
 
 # ---------------------------------------------------------- host-side helpers
+def optimise_widths(model, c_rng=1e4, rng_term=False):
+    """Section 6 widths of one level from an error model (dict as Context.error_model
+    returns); host only."""
+    m = error_model_struct(model)
+    out = WidthPlan()
+    out.struct_size = C.sizeof(WidthPlan)
+    check(lib().mlmc_optimise_widths(C.byref(m), float(c_rng), 1 if rng_term else 0, C.byref(out)))
+    return out.as_dict()
+
+
 def build_table(q, arith="fp32", frac_bits=0):
     dt = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "fixed": np.int32}[arith]
     out = np.zeros(1 << q, dtype=dt)

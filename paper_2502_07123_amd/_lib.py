@@ -129,6 +129,44 @@ class ServerConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("max_active", C.c_uint32), ("run", RunConfig)]
 
 
+class ErrorModel(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("level", C.c_int32), ("scheme", C.c_int32),
+                ("table_bits", C.c_int32), ("n_paths", C.c_uint64), ("used", C.c_int32 * NVARS),
+                ("e", C.c_int32 * NVARS), ("S", C.c_double * NVARS), ("R", C.c_double * NVARS),
+                ("V_level", C.c_double), ("mse", C.c_double)]
+
+    def as_dict(self):
+        return {"level": self.level, "scheme": self.scheme, "table_bits": self.table_bits,
+                "n_paths": self.n_paths, "used": list(self.used), "e": list(self.e), "S": list(self.S),
+                "R": list(self.R), "V_level": self.V_level, "mse": self.mse}
+
+
+class WidthPlan(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("best_uniform", C.c_int32), ("lambda_", C.c_double),
+                ("objective", C.c_double), ("objective_uniform", C.c_double), ("v_indep", C.c_double),
+                ("cost", C.c_double), ("d_real", C.c_double * NVARS), ("d_int", C.c_int32 * NVARS),
+                ("word_bits", C.c_int32 * NVARS), ("frac_bits", C.c_int32 * NVARS)]
+
+    def as_dict(self):
+        return {"best_uniform": self.best_uniform, "lambda": self.lambda_, "objective": self.objective,
+                "objective_uniform": self.objective_uniform, "v_indep": self.v_indep, "cost": self.cost,
+                "d_real": list(self.d_real), "d_int": list(self.d_int), "word_bits": list(self.word_bits),
+                "frac_bits": list(self.frac_bits)}
+
+
+def error_model_struct(d):
+    """An ErrorModel from a mapping with its fields (lists for the per-variable ones)."""
+    m = ErrorModel()
+    m.struct_size = C.sizeof(ErrorModel)
+    for k in ("level", "scheme", "table_bits", "n_paths", "V_level", "mse"):
+        setattr(m, k, d[k])
+    for k in ("used", "e", "S", "R"):
+        arr = getattr(m, k)
+        for i in range(NVARS):
+            arr[i] = d[k][i]
+    return m
+
+
 class ServerStats(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("pad", C.c_uint32), ("flights", C.c_uint64),
                 ("works", C.c_uint64), ("requests_done", C.c_uint64), ("queued", C.c_uint64),
@@ -177,6 +215,8 @@ def lib():
         "mlmc_poll": (st, [vp, u64, P(Result)]),
         "mlmc_poll_done": (st, [vp, u32, P(u64), P(Result), P(u32)]),
         "mlmc_server_stats_get": (st, [vp, P(ServerStats)]),
+        "mlmc_error_model_compute": (st, [vp, P(Problem), i32, u64, i32, u64, u32, P(ErrorModel)]),
+        "mlmc_optimise_widths": (st, [P(ErrorModel), C.c_double, i32, P(WidthPlan)]),
         "mlmc_server_stop": (st, [vp]),
         "mlmc_build_table": (st, [i32, i32, i32, vp]),
         "mlmc_build_rng_table": (st, [i32, i32, P(C.c_double), P(C.c_uint16), P(i32)]),
@@ -201,7 +241,7 @@ EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_c
             "mlmc_get_tuning", "mlmc_set_tuning",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_poll_done", "mlmc_server_stats_get",
-            "mlmc_server_stop",
+            "mlmc_server_stop", "mlmc_error_model_compute", "mlmc_optimise_widths",
             "mlmc_build_table", "mlmc_build_rng_table", "mlmc_stream_words", "mlmc_validate", "mlmc_check_paths_host",
             "mlmc_allocate")
 

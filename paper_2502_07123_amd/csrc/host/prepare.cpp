@@ -408,6 +408,23 @@ static FxOp add_op(const int* f, const int* w, int fa, int fb, int d) {
     return FxOp{fm - fa, fm - fb, fm - f[d], w[d]};
 }
 
+// Method 1's MSE E[(Z - T_q[k(Z)])^2] = 1 - 2^-q sum_k T_q[k]^2 (T_q[k] is the mean
+// of Z on interval k, so the error is orthogonal to the table; Section 3.1).
+double table_mse(int q) {
+    const auto& T = method1_table(q);
+    long double s = 0.0L;
+    for (long double t : T) s += t * t;
+    return static_cast<double>(1.0L - s / static_cast<long double>(uint64_t(1) << q));
+}
+
+// The largest |T_q[k]| (the end intervals' means).
+double table_max_abs(int q) {
+    const auto& T = method1_table(q);
+    long double m = 0.0L;
+    for (long double t : T) m = std::max(m, t < 0 ? -t : t);
+    return static_cast<double>(m);
+}
+
 // The table values of (q, method) rounded once to FP32 (Method 1 from its exact
 // interval means, Methods 2/3 from their FP64 values), kept for the process.
 static const std::vector<float>& table_values_f32(int q, int method) {

@@ -47,4 +47,8 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
 
 int popcount32(uint32_t v);
 
+// Method 1 table statistics (Section 3.1): its MSE and its largest |value|.
+double table_mse(int q);
+double table_max_abs(int q);
+
 }  // namespace mlmc
