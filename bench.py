@@ -199,6 +199,8 @@ def main():
     # two marshalled batches alternate so that the host prepares step k + 1 while the
     # GPU runs step k; each step draws fresh paths (path offsets advance)
     batches = [ctx.sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, 0)) for _ in range(2)]
+    # launch geometry for this work list by the library's tuner (untimed)
+    tuning = ctx.autotune(batches[0], reps=5)
     off = N_PILOT
     ests = []
 
@@ -258,6 +260,7 @@ def main():
         "estimate": float(np.mean([e[0] for e in ests])),
         "rmse_bound": float(ests[-1][1]),
         "N_approx": [int(x) for x in Na], "N_corr": [int(x) for x in Nc],
+        "tuning": tuning,
         "kernels": [{"estimator": s["estimator"], "arith": s["arith"], "fields": s["fields"],
                      "launches": s["launches"], "ms": s["ms"],
                      "path_steps_per_s": s["path_steps"] / (s["ms"] * 1e-3)} for s in stats],

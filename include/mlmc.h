@@ -269,6 +269,19 @@ typedef struct mlmc_tuning {
 } mlmc_tuning;
 
 mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out);
+/* Chooses the launch geometry for a work list (host wall time of whole launch
+ * sequences, median of `reps` after a warm-up run): one pass of coordinate descent
+ * over block_table {256, 512, 1024}, block_exact {64, 128, 256}, tile_steps
+ * {2^14..2^18}, blocks_per_cu {2, 4, 8, 16}, min_tiles {512..4096} and zb_max_paths
+ * {0, 2^13, 2^15, 2^17}, starting from the context's current geometry and keeping
+ * a change only when it is faster.  Sets the result on the context and copies it to
+ * out (out->struct_size must be set).  The works' sums are written by every trial
+ * run (the last trial's remain); sums of the same work can differ in FP64 rounding
+ * between geometries (a different tile split), so tune before pricing.  Errors:
+ * those of mlmc_level_sums_batch, MLMC_E_BUSY while a server runs, MLMC_E_INVALID
+ * (reps outside 1..100). */
+mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works, uint32_t reps,
+                          mlmc_tuning* out);
 mlmc_status mlmc_set_tuning(mlmc_context* ctx, const mlmc_tuning* t);   /* MLMC_E_INVALID if out of range */
 
 mlmc_status mlmc_set_timing(mlmc_context* ctx, int32_t on);  /* also clears the stats */

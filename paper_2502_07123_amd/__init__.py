@@ -115,6 +115,13 @@ class Context:
             setattr(t, k, v)
         check(lib().mlmc_set_tuning(self.h, C.byref(t)), self.h)
 
+    def autotune(self, batch, reps=5):
+        """Launch geometry chosen for a SumsBatch's works (mlmc_autotune); returns it."""
+        t = Tuning()
+        t.struct_size = C.sizeof(Tuning)
+        check(lib().mlmc_autotune(self.h, batch.n, batch._works, reps, C.byref(t)), self.h)
+        return t.as_dict()
+
     def set_timing(self, on=True):
         check(lib().mlmc_set_timing(self.h, 1 if on else 0), self.h)
 

@@ -207,6 +207,7 @@ def lib():
         "mlmc_set_timing": (st, [vp, i32]),
         "mlmc_get_tuning": (st, [vp, P(Tuning)]),
         "mlmc_set_tuning": (st, [vp, P(Tuning)]),
+        "mlmc_autotune": (st, [vp, u32, P(LevelWork), u32, P(Tuning)]),
         "mlmc_kernel_stats": (st, [vp, P(KernelStat), u32, P(u32)]),
         "mlmc_estimate": (st, [vp, P(Problem), P(RunConfig), u64, u32, P(Result)]),
         "mlmc_estimate_batch": (st, [vp, u32, P(Problem), P(RunConfig), u64, P(Result)]),
@@ -238,7 +239,7 @@ def lib():
 EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_context_create",
             "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_batch",
             "mlmc_level_sums_enqueue", "mlmc_level_sums_wait", "mlmc_set_timing",
-            "mlmc_get_tuning", "mlmc_set_tuning",
+            "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_poll_done", "mlmc_server_stats_get",
             "mlmc_server_stop", "mlmc_error_model_compute", "mlmc_optimise_widths",

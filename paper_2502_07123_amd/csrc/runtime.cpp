@@ -998,6 +998,77 @@ mlmc_status mlmc_set_tuning(mlmc_context* ctx, const mlmc_tuning* t) {
     return MLMC_OK;
 }
 
+// Launch-geometry tuner: coordinate descent over the tuning fields, each candidate
+// timed (host wall clock around whole synchronous launch sequences: planning,
+// upload, kernels, reduction and download) on the caller's own work list.
+mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works, uint32_t reps,
+                          mlmc_tuning* out) {
+    if (!ctx || !out) return MLMC_E_INVALID;
+    if (out->struct_size != sizeof(mlmc_tuning)) return fail(ctx, MLMC_E_VERSION, "mlmc_tuning.struct_size mismatch");
+    if (reps < 1 || reps > 100) return fail(ctx, MLMC_E_INVALID, "reps must be 1..100");
+    if (ctx->server) return fail(ctx, MLMC_E_BUSY, "stop the server before tuning");
+    std::vector<WorkSpec> ws;
+    mlmc_status s = batch_specs(ctx, n, works, ws);
+    if (s != MLMC_OK) return s;
+    {
+        std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+        if ((s = drain_flights(ctx)) != MLMC_OK) return s;
+    }
+    std::vector<SlotDev> res;
+    auto measure = [&](const Tuning& t, double& sec) -> mlmc_status {
+        {
+            std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+            ctx->tune = t;
+        }
+        mlmc_status st = run_works(ctx, ws, res);            // warm (tables, pinned buffers)
+        if (st != MLMC_OK) return st;
+        std::vector<double> ts;
+        for (uint32_t r = 0; r < reps; ++r) {
+            const double t0 = now_seconds();
+            if ((st = run_works(ctx, ws, res)) != MLMC_OK) return st;
+            ts.push_back(now_seconds() - t0);
+        }
+        std::sort(ts.begin(), ts.end());
+        sec = ts[ts.size() / 2];
+        return MLMC_OK;
+    };
+    Tuning best = ctx->tune;
+    double best_s = 0.0;
+    if ((s = measure(best, best_s)) != MLMC_OK) return s;
+    auto try_field = [&](auto set, std::initializer_list<uint64_t> values) -> mlmc_status {
+        for (uint64_t v : values) {
+            Tuning t = best;
+            set(t, v);
+            double sec = 0.0;
+            const mlmc_status st = measure(t, sec);
+            if (st == MLMC_E_NOMEM) continue;                 // a geometry the workspace cannot hold
+            if (st != MLMC_OK) return st;
+            if (sec < best_s) {
+                best_s = sec;
+                best = t;
+            }
+        }
+        return MLMC_OK;
+    };
+    const mlmc_status r =
+        [&]() -> mlmc_status {
+            mlmc_status st;
+            if ((st = try_field([](Tuning& t, uint64_t v) { t.block_table = uint32_t(v); }, {256, 512, 1024})) != MLMC_OK) return st;
+            if ((st = try_field([](Tuning& t, uint64_t v) { t.block_exact = uint32_t(v); }, {64, 128, 256})) != MLMC_OK) return st;
+            if ((st = try_field([](Tuning& t, uint64_t v) { t.tile_steps = uint32_t(v); },
+                                {1u << 14, 1u << 15, 1u << 16, 1u << 17, 1u << 18})) != MLMC_OK) return st;
+            if ((st = try_field([](Tuning& t, uint64_t v) { t.blocks_per_cu = uint32_t(v); }, {2, 4, 8, 16})) != MLMC_OK) return st;
+            if ((st = try_field([](Tuning& t, uint64_t v) { t.min_tiles = uint32_t(v); }, {512, 1024, 2048, 4096})) != MLMC_OK) return st;
+            return try_field([](Tuning& t, uint64_t v) { t.zb_max_paths = v; }, {0, 1u << 13, 1u << 15, 1u << 17});
+        }();
+    {
+        std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+        ctx->tune = best;
+    }
+    if (r != MLMC_OK) return r;
+    return mlmc_get_tuning(ctx, out);
+}
+
 mlmc_status mlmc_set_timing(mlmc_context* ctx, int32_t on) {
     if (!ctx) return MLMC_E_INVALID;
     std::lock_guard<std::mutex> lock(ctx->dev_mtx);

@@ -257,3 +257,33 @@ def test_server_poll_and_stop(ctx):
         assert ctx.poll_done(8) == []       # taken by mlmc_poll
     finally:
         ctx.server_stop()
+
+
+def test_autotune_keeps_results_valid():
+    """mlmc_autotune picks a geometry from its candidate sets, leaves it on the
+    context, and the work list's results stay what they must be: exact integer sums
+    identical (they do not depend on the tile split), FP64 sums within rounding."""
+    c = M.Context(0, workspace_bytes=256 << 20)
+    try:
+        items = _items()
+        before = c.level_sums_batch(items)
+        b = c.sums_batch(items)
+        t = c.autotune(b, reps=2)
+        assert t == c.get_tuning()
+        assert t["block_table"] in (256, 512, 1024) and t["block_exact"] in (64, 128, 256)
+        assert t["tile_steps"] in [1 << k for k in range(14, 19)] and t["blocks_per_cu"] in (2, 4, 8, 16)
+        assert t["min_tiles"] in (512, 1024, 2048, 4096) and t["zb_max_paths"] in (0, 1 << 13, 1 << 15, 1 << 17)
+        after = c.level_sums_batch(items)
+        for i, (a, z) in enumerate(zip(before, after)):
+            for p in a:
+                assert a[p]["n"] == z[p]["n"] and a[p]["isum1"] == z[p]["isum1"] and a[p]["isum2"] == z[p]["isum2"]
+                n = a[p]["n"]
+                for k1, k2 in (("sum1", "sum2"), ("esum1", "esum2")):
+                    # |Y| summed <= sqrt(n sum Y^2): two summation orders differ by at most
+                    # 2 n 2^-53 times that (and 2 n 2^-53 sum Y^2 for the squares)
+                    tol1 = 4 * n * 2.0 ** -53 * (n * a[p][k2]) ** 0.5 + 1e-300
+                    tol2 = 4 * n * 2.0 ** -53 * a[p][k2] + 1e-300
+                    assert abs(a[p][k1] - z[p][k1]) <= tol1, (i, p, k1)
+                    assert abs(a[p][k2] - z[p][k2]) <= tol2, (i, p, k2)
+    finally:
+        c.close()
