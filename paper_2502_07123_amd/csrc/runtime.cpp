@@ -135,6 +135,8 @@ void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
 mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out) {
     const hipError_t e = hipEventSynchronize(f.done);
     ctx->ev_plain.push_back(f.done);
+    if (f.up) ctx->ev_plain.push_back(f.up);        // completed before the flight's kernels
+    if (f.join) ctx->ev_plain.push_back(f.join);    // completed before its reduction
     PinnedBuf& pb = ctx->pins[f.pin];
     pb.busy = false;
     if (e != hipSuccess) {
@@ -411,9 +413,20 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     if (!ntiles[0].empty()) std::memcpy(h + (o_nt0 - o_lvl), ntiles[0].data(), ntiles[0].size() * sizeof(TileDev));
     if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
     hipStream_t s = ctx->stream;
-    const hipError_t ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s);
+    // the plan goes up on the context's copy stream, so it overlaps the kernels of the
+    // flights still running (its ring region and staging buffer are its own); the
+    // kernels wait for it through an event
+    if ((st = take_event(ctx, false, f.up)) != MLMC_OK) {
+        release();
+        return st;
+    }
+    hipError_t ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, ctx->copy_stream);
+    if (ue == hipSuccess) ue = hipEventRecord(f.up, ctx->copy_stream);
+    if (ue == hipSuccess) ue = hipStreamWaitEvent(s, f.up, 0);
     if (ue != hipSuccess) {
         release();
+        ctx->ev_plain.push_back(f.up);
+        f.up = nullptr;
         return fail(ctx, MLMC_E_DEVICE, std::string("upload: ") + hipGetErrorString(ue));
     }
     launched = true;                      // from here the staging buffer belongs to the flight
@@ -431,12 +444,23 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
                               reinterpret_cast<const WorkDev*>(d + o_work),
                               reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab));
     }
-    // path kernels, one per variant, then the fixed-order reduction of each work
+    // path kernels, one per variant, then the fixed-order reduction of each work.
+    // Table-only (approximate) groups do not wait for the normals-ahead kernel: when a
+    // flight has both kinds they run on the context's second stream, concurrently with
+    // the exact-normal groups, and join before the reduction.
     const uint32_t max_grid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * ctx->tune.blocks_per_cu;
+    bool has_table = false, has_exact = false;
+    for (auto& kv : groups) {
+        if (kv.second.t1 == kv.second.t0) continue;
+        (kv.second.v.est == MLMC_EST_APPROX ? has_table : has_exact) = true;
+    }
+    const bool fork = has_table && has_exact && ctx->aux_stream;
+    if (fork) HIPCHK(hipStreamWaitEvent(ctx->aux_stream, f.up, 0));
     for (auto& kv : groups) {
         LaunchGroup& g = kv.second;
         const uint32_t nt = g.t1 - g.t0;
         if (!nt) continue;
+        hipStream_t gs = (fork && g.v.est == MLMC_EST_APPROX) ? ctx->aux_stream : s;
         const uint32_t grid = std::min(nt, max_grid);
         Flight::Timed tm{};
         if (ctx->timing) {
@@ -445,14 +469,19 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             if ((st = take_event(ctx, true, tm.e0)) != MLMC_OK) return st;
             if ((st = take_event(ctx, true, tm.e1)) != MLMC_OK) return st;
             f.timed.push_back(tm);
-            HIPCHK(hipEventRecord(tm.e0, s));
+            HIPCHK(hipEventRecord(tm.e0, gs));
         }
-        HIPCHK(launch_paths(g.vi, grid, g.block, g.lds, s,
+        HIPCHK(launch_paths(g.vi, grid, g.block, g.lds, gs,
                             reinterpret_cast<const TileDev*>(d + o_tile) + g.t0, nt,
                             reinterpret_cast<const WorkDev*>(d + o_work),
                             reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab,
                             reinterpret_cast<SlotDev*>(d + o_slot)));
-        if (ctx->timing) HIPCHK(hipEventRecord(tm.e1, s));
+        if (ctx->timing) HIPCHK(hipEventRecord(tm.e1, gs));
+    }
+    if (fork) {
+        if ((st = take_event(ctx, false, f.join)) != MLMC_OK) return st;
+        HIPCHK(hipEventRecord(f.join, ctx->aux_stream));
+        HIPCHK(hipStreamWaitEvent(s, f.join, 0));
     }
     HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s, reinterpret_cast<const SlotDev*>(d + o_slot),
                          reinterpret_cast<const ReduceDev*>(d + o_red), reinterpret_cast<SlotDev*>(d + o_res)));
@@ -833,7 +862,18 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
     ctx->ws_bytes = workspace_bytes;
+    if (hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return MLMC_E_DEVICE;
+    }
+    if (hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(ctx->copy_stream);
+        delete ctx;
+        return MLMC_E_DEVICE;
+    }
     if (hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        (void)hipStreamDestroy(ctx->copy_stream);
+        (void)hipStreamDestroy(ctx->aux_stream);
         delete ctx;
         return MLMC_E_DEVICE;
     }
@@ -841,6 +881,8 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
         ctx->ws = static_cast<uint8_t*>(workspace);
     } else {
         if (hipMalloc(reinterpret_cast<void**>(&ctx->ws), workspace_bytes) != hipSuccess) {
+            (void)hipStreamDestroy(ctx->copy_stream);
+            (void)hipStreamDestroy(ctx->aux_stream);
             delete ctx;
             return MLMC_E_NOMEM;
         }
@@ -857,8 +899,12 @@ void mlmc_context_destroy(mlmc_context* ctx) {
         std::lock_guard<std::mutex> lock(ctx->dev_mtx);
         (void)drain_flights(ctx);
     }
+    if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
+    if (ctx->aux_stream) (void)hipStreamSynchronize(ctx->aux_stream);
     for (hipEvent_t e : ctx->ev_plain) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_timed) (void)hipEventDestroy(e);
+    if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
+    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     for (auto& pb : ctx->pins)
         if (pb.p) (void)hipHostFree(pb.p);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);

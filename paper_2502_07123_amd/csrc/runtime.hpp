@@ -66,6 +66,8 @@ struct Flight {
     size_t down_off = 0;
     uint32_t n_works = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t up = nullptr;        // the plan's upload (on the context's copy stream)
+    hipEvent_t join = nullptr;      // table-only kernels done on the second stream
     struct Timed {
         Variant v;
         uint64_t steps = 0;
@@ -82,6 +84,8 @@ struct Flight {
 struct mlmc_context {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;   // plan uploads (default priority, non-blocking)
+    hipStream_t aux_stream = nullptr;    // table-only path kernels beside the exact-normal ones
     bool own_ws = false;
     uint8_t* ws = nullptr;
     uint64_t ws_bytes = 0;
