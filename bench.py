@@ -402,7 +402,6 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256)
                 q.eps = float(eps[i])
                 q.seed = SEED
                 q.nested = 1 if nested else 0
-            ctx.set_timing(True)
             ctx.server_start(_run_cfg(M, nested, 1e-3, costs), max_active=max_active)
             lag = np.zeros(n)
             lat = np.full(n, np.nan)
@@ -451,8 +450,6 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256)
             sst = ctx.server_stats()
             wall = time.perf_counter() - t0
             ctx.server_stop()
-            kst = ctx.kernel_stats()
-            ctx.set_timing(False)
             ok = meas & ~np.isnan(lat)
             span = (np.nanmax(done_at[ok]) - warm) if ok.any() else float("nan")
             cf_err = []
@@ -470,7 +467,7 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256)
                 "submit_lag_p99_ms": _pct(lag[meas] * 1e3, 99),
                 "closed_form_checked": int(cf_err.size),
                 "rms_err_over_eps": float(np.sqrt(np.mean(cf_err ** 2))) if cf_err.size else None,
-                "wall_s": wall, "path_kernel_busy_s": sum(k["ms"] for k in kst) * 1e-3,
+                "wall_s": wall,
                 "scheduler": {k: sst[k] for k in ("flights", "works", "plan_seconds", "land_seconds",
                                                   "idle_seconds")},
             })

@@ -258,7 +258,13 @@ typedef struct mlmc_kernel_stat {
  *   zb_max_paths, zb_max_positions: exact-normal works (levels >= 2) with at most
  *                 this many paths and paths*2^level stream positions get their
  *                 normals computed ahead by a separate kernel (off the paths'
- *                 sequential chains); 0 disables. */
+ *                 sequential chains); 0 disables.
+ *   overlap_min_steps: launch sequences of at least this many fine path-steps
+ *                 upload their plan on a second (copy) stream while earlier
+ *                 sequences compute, and run their approximate-estimator kernels on
+ *                 a third stream beside the exact-normal ones; smaller sequences use
+ *                 the context's stream alone (each cross-stream dependency costs the
+ *                 host ~10 us).  Default 2^26. */
 typedef struct mlmc_tuning {
     uint32_t struct_size;
     uint32_t block_table, block_exact;
@@ -266,14 +272,17 @@ typedef struct mlmc_tuning {
     uint32_t blocks_per_cu;
     uint32_t min_tiles;
     uint64_t zb_max_paths, zb_max_positions;
+    uint64_t overlap_min_steps;
 } mlmc_tuning;
 
 mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out);
-/* Chooses the launch geometry for a work list (host wall time of whole launch
- * sequences, median of `reps` after a warm-up run): one pass of coordinate descent
+/* Chooses the launch geometry for a work list (host wall time per launch sequence
+ * with `reps` sequences enqueued back to back, as a pipelined caller or the server
+ * runs them, after a warm-up run): one pass of coordinate descent
  * over block_table {256, 512, 1024}, block_exact {64, 128, 256}, tile_steps
  * {2^14..2^18}, blocks_per_cu {2, 4, 8, 16}, min_tiles {512..4096} and zb_max_paths
- * {0, 2^13, 2^15, 2^17}, starting from the context's current geometry and keeping
+ * {0, 2^13, 2^15, 2^17} and overlap_min_steps {0, 2^24, 2^26, 2^28, never},
+ * starting from the context's current geometry and keeping
  * a change only when it is faster.  Sets the result on the context and copies it to
  * out (out->struct_size must be set).  The works' sums are written by every trial
  * run (the last trial's remain); sums of the same work can differ in FP64 rounding

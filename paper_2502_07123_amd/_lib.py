@@ -93,7 +93,8 @@ class KernelStat(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("block_table", C.c_uint32), ("block_exact", C.c_uint32),
                 ("tile_steps", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("min_tiles", C.c_uint32),
-                ("zb_max_paths", C.c_uint64), ("zb_max_positions", C.c_uint64)]
+                ("zb_max_paths", C.c_uint64), ("zb_max_positions", C.c_uint64),
+                ("overlap_min_steps", C.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}

@@ -413,19 +413,27 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     if (!ntiles[0].empty()) std::memcpy(h + (o_nt0 - o_lvl), ntiles[0].data(), ntiles[0].size() * sizeof(TileDev));
     if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
     hipStream_t s = ctx->stream;
-    // the plan goes up on the context's copy stream, so it overlaps the kernels of the
-    // flights still running (its ring region and staging buffer are its own); the
-    // kernels wait for it through an event
-    if ((st = take_event(ctx, false, f.up)) != MLMC_OK) {
-        release();
-        return st;
+    uint64_t flight_steps = 0;
+    for (const WorkSpec& w : works) flight_steps += w.n << w.level;
+    const bool overlap = flight_steps >= ctx->tune.overlap_min_steps;
+    // large flights: the plan goes up on the context's copy stream, so it overlaps the
+    // kernels of the flights still running (its ring region and staging buffer are its
+    // own); the kernels wait for it through an event
+    hipError_t ue = hipSuccess;
+    if (overlap) {
+        if ((st = take_event(ctx, false, f.up)) != MLMC_OK) {
+            release();
+            return st;
+        }
+        ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, ctx->copy_stream);
+        if (ue == hipSuccess) ue = hipEventRecord(f.up, ctx->copy_stream);
+        if (ue == hipSuccess) ue = hipStreamWaitEvent(s, f.up, 0);
+    } else {
+        ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s);
     }
-    hipError_t ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, ctx->copy_stream);
-    if (ue == hipSuccess) ue = hipEventRecord(f.up, ctx->copy_stream);
-    if (ue == hipSuccess) ue = hipStreamWaitEvent(s, f.up, 0);
     if (ue != hipSuccess) {
         release();
-        ctx->ev_plain.push_back(f.up);
+        if (f.up) ctx->ev_plain.push_back(f.up);
         f.up = nullptr;
         return fail(ctx, MLMC_E_DEVICE, std::string("upload: ") + hipGetErrorString(ue));
     }
@@ -454,7 +462,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         if (kv.second.t1 == kv.second.t0) continue;
         (kv.second.v.est == MLMC_EST_APPROX ? has_table : has_exact) = true;
     }
-    const bool fork = has_table && has_exact && ctx->aux_stream;
+    const bool fork = overlap && has_table && has_exact && ctx->aux_stream;
     if (fork) HIPCHK(hipStreamWaitEvent(ctx->aux_stream, f.up, 0));
     for (auto& kv : groups) {
         LaunchGroup& g = kv.second;
@@ -1023,6 +1031,7 @@ mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out) {
     out->min_tiles = ctx->tune.min_tiles;
     out->zb_max_paths = ctx->tune.zb_max_paths;
     out->zb_max_positions = ctx->tune.zb_max_positions;
+    out->overlap_min_steps = ctx->tune.overlap_min_steps;
     return MLMC_OK;
 }
 
@@ -1041,12 +1050,13 @@ mlmc_status mlmc_set_tuning(mlmc_context* ctx, const mlmc_tuning* t) {
     ctx->tune.min_tiles = t->min_tiles;
     ctx->tune.zb_max_paths = t->zb_max_paths;
     ctx->tune.zb_max_positions = t->zb_max_positions;
+    ctx->tune.overlap_min_steps = t->overlap_min_steps;
     return MLMC_OK;
 }
 
 // Launch-geometry tuner: coordinate descent over the tuning fields, each candidate
-// timed (host wall clock around whole synchronous launch sequences: planning,
-// upload, kernels, reduction and download) on the caller's own work list.
+// timed on the caller's own work list (host wall clock per launch sequence, planning,
+// upload, kernels, reduction and download, with sequences pipelined).
 mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works, uint32_t reps,
                           mlmc_tuning* out) {
     if (!ctx || !out) return MLMC_E_INVALID;
@@ -1061,6 +1071,8 @@ mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* 
         if ((s = drain_flights(ctx)) != MLMC_OK) return s;
     }
     std::vector<SlotDev> res;
+    // steady-state time per launch sequence: `reps` sequences enqueued back to back
+    // (as a pipelined caller or the server runs them), then all landed
     auto measure = [&](const Tuning& t, double& sec) -> mlmc_status {
         {
             std::lock_guard<std::mutex> lock(ctx->dev_mtx);
@@ -1068,14 +1080,18 @@ mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* 
         }
         mlmc_status st = run_works(ctx, ws, res);            // warm (tables, pinned buffers)
         if (st != MLMC_OK) return st;
-        std::vector<double> ts;
+        std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+        const double t0 = now_seconds();
         for (uint32_t r = 0; r < reps; ++r) {
-            const double t0 = now_seconds();
-            if ((st = run_works(ctx, ws, res)) != MLMC_OK) return st;
-            ts.push_back(now_seconds() - t0);
+            Flight f;
+            if ((st = launch_flight(ctx, ws, f)) != MLMC_OK) {
+                drain_flights(ctx);
+                return st;
+            }
+            ctx->flights.push_back(std::move(f));
         }
-        std::sort(ts.begin(), ts.end());
-        sec = ts[ts.size() / 2];
+        if ((st = drain_flights(ctx)) != MLMC_OK) return st;
+        sec = (now_seconds() - t0) / reps;
         return MLMC_OK;
     };
     Tuning best = ctx->tune;
@@ -1105,7 +1121,9 @@ mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* 
                                 {1u << 14, 1u << 15, 1u << 16, 1u << 17, 1u << 18})) != MLMC_OK) return st;
             if ((st = try_field([](Tuning& t, uint64_t v) { t.blocks_per_cu = uint32_t(v); }, {2, 4, 8, 16})) != MLMC_OK) return st;
             if ((st = try_field([](Tuning& t, uint64_t v) { t.min_tiles = uint32_t(v); }, {512, 1024, 2048, 4096})) != MLMC_OK) return st;
-            return try_field([](Tuning& t, uint64_t v) { t.zb_max_paths = v; }, {0, 1u << 13, 1u << 15, 1u << 17});
+            if ((st = try_field([](Tuning& t, uint64_t v) { t.zb_max_paths = v; }, {0, 1u << 13, 1u << 15, 1u << 17})) != MLMC_OK) return st;
+            return try_field([](Tuning& t, uint64_t v) { t.overlap_min_steps = v; },
+                             {0, uint64_t(1) << 24, uint64_t(1) << 26, uint64_t(1) << 28, UINT64_MAX});
         }();
     {
         std::lock_guard<std::mutex> lock(ctx->dev_mtx);

@@ -33,6 +33,10 @@ struct Tuning {
     // stream positions) get their normals computed ahead, off the paths' chains
     uint64_t zb_max_paths = 1u << 15;
     uint64_t zb_max_positions = 1u << 22;
+    // flights of at least this many fine path-steps upload on the copy stream and run
+    // their table-only kernels on the second stream (each cross-stream wait costs the
+    // host about 10 us, which small flights do not win back)
+    uint64_t overlap_min_steps = uint64_t(1) << 26;
 };
 
 // One (option, level, estimator) path range of a launch.

@@ -273,6 +273,7 @@ def test_autotune_keeps_results_valid():
         assert t["block_table"] in (256, 512, 1024) and t["block_exact"] in (64, 128, 256)
         assert t["tile_steps"] in [1 << k for k in range(14, 19)] and t["blocks_per_cu"] in (2, 4, 8, 16)
         assert t["min_tiles"] in (512, 1024, 2048, 4096) and t["zb_max_paths"] in (0, 1 << 13, 1 << 15, 1 << 17)
+        assert t["overlap_min_steps"] in (0, 1 << 24, 1 << 26, 1 << 28, (1 << 64) - 1)
         after = c.level_sums_batch(items)
         for i, (a, z) in enumerate(zip(before, after)):
             for p in a:
