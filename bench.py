@@ -236,7 +236,7 @@ def main():
 
     # roofline of the dominant kernel (largest event time in the timed region)
     dom = max(stats, key=lambda s: s["ms"])
-    per_launch_steps = dom["path_steps"] / dom["launches"]
+    per_step_steps = dom["path_steps"] / args.steps
     # algorithmic ops of that kernel's works, level by level (its level mix)
     if dom["estimator"] == M.EST_APPROX:
         mix = [(l, int(Na[l])) for l in range(LEVELS)]
@@ -244,7 +244,8 @@ def main():
         mix = [(l, int(Nc[l])) for l in range(LEVELS)]
     ops = sum(n * (1 << l) * alg_ops_per_step(dom["estimator"], dom["fields"], dom["scheme"], l)
               for l, n in mix)
-    avg_s = dom["ms"] / dom["launches"] * 1e-3
+    # the kernel's time per step (its launches of one step together cover the mix)
+    avg_s = dom["ms"] / args.steps * 1e-3
     achieved = ops / avg_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_valu() / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / peak_valu(),
@@ -252,9 +253,10 @@ def main():
                                             f"{'true' if dom['scheme'] else 'false'}, {dom['payoffs']}, "
                                             f"{'true' if dom['track'] else 'false'}, {dom['fields']}>"),
                 "kernel": {"estimator": dom["estimator"], "fields": dom["fields"],
+                           "launches_per_step": dom["launches"] / args.steps,
                            "avg_launch_ms": dom["ms"] / dom["launches"],
-                           "path_steps_per_launch": per_launch_steps,
-                           "alg_lane_ops_per_launch": ops}}
+                           "path_steps_per_step": per_step_steps,
+                           "alg_lane_ops_per_step": ops}}
 
     extra = {
         "estimate": float(np.mean([e[0] for e in ests])),

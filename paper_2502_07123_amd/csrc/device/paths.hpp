@@ -560,8 +560,9 @@ struct PathBody {
 
     // ---- level 0 of the FP32 approximate estimator from a table of per-index
     // samples: Y(k) is computed once per level (ysample) into LDS and every path adds
-    // its own sample, so the sums equal those of the per-path code summed in the
-    // same order, with one table read per path instead of the path arithmetic.
+    // its own sample (the same values as the per-path code; per group in four
+    // interleaved partial sums), with one table read per path instead of the path
+    // arithmetic.
     // (Fixed point keeps the index histogram: its exact integer sums per path would
     // cost more than a count.)
     static constexpr bool YTAB = HIST && !FIXED;
@@ -604,48 +605,63 @@ struct PathBody {
         const bool full = path0 >= W.path_begin && path0 + WPB <= W.path_end;
         const int q = L.q;
         const uint32_t E = L.table_entries;
+        // path j of the group adds to partial sum j mod 4 and the partials join the
+        // accumulator as (p0 + p1) + (p2 + p3): four short dependent FP64 chains
+        // instead of one of length 4F, in the same order in both branches
+        double p1[4][NP], p2[4][NP];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int slot = 0; slot < NP; ++slot) p1[c][slot] = p2[c][slot] = 0.0;
         if (full && !W.debug) {
 #pragma unroll
             for (int wi = 0; wi < 4; ++wi)
 #pragma unroll
                 for (int fi = 0; fi < F; ++fi) {
                     const uint32_t k = index_field(wd[wi], fi, q);
+                    const int c = (wi * F + fi) & 3;
 #pragma unroll
                     for (int slot = 0; slot < NP; ++slot) {
                         const double Y = static_cast<double>(ytab[slot * E + k]);
-                        acc.s1[slot] += Y;
-                        acc.s2[slot] = fma(Y, Y, acc.s2[slot]);
+                        p1[c][slot] += Y;
+                        p2[c][slot] = fma(Y, Y, p2[c][slot]);
                     }
                 }
             acc.n += WPB;
-            return;
-        }
+        } else {
 #pragma unroll
-        for (int wi = 0; wi < 4; ++wi) {
+            for (int wi = 0; wi < 4; ++wi) {
 #pragma unroll
-            for (int fi = 0; fi < F; ++fi) {
-                const uint32_t J = wd[wi];
-                const uint32_t k = index_field(J, fi, q);
-                const uint64_t pidx = path0 + uint64_t(wi * F + fi);
-                if (full || (pidx >= W.path_begin && pidx < W.path_end)) {
-                    if (W.debug) {
-                        FSide<ExactT> ex;
-                        FSide<AT> ap;
-                        XSide ax;
-                        level0_path(L, tab, k, ap, ax);
-                        Acc<NP> scratch;
-                        acc_zero(scratch);
-                        finish(L, W, pidx, ex, ap, ax, J, k, scratch);
+                for (int fi = 0; fi < F; ++fi) {
+                    const uint32_t J = wd[wi];
+                    const uint32_t k = index_field(J, fi, q);
+                    const uint64_t pidx = path0 + uint64_t(wi * F + fi);
+                    const int c = (wi * F + fi) & 3;
+                    if (full || (pidx >= W.path_begin && pidx < W.path_end)) {
+                        if (W.debug) {
+                            FSide<ExactT> ex;
+                            FSide<AT> ap;
+                            XSide ax;
+                            level0_path(L, tab, k, ap, ax);
+                            Acc<NP> scratch;
+                            acc_zero(scratch);
+                            finish(L, W, pidx, ex, ap, ax, J, k, scratch);
+                        }
+#pragma unroll
+                        for (int slot = 0; slot < NP; ++slot) {
+                            const double Y = static_cast<double>(ytab[slot * E + k]);
+                            p1[c][slot] += Y;
+                            p2[c][slot] = fma(Y, Y, p2[c][slot]);
+                        }
+                        acc.n += 1;
                     }
-#pragma unroll
-                    for (int slot = 0; slot < NP; ++slot) {
-                        const double Y = static_cast<double>(ytab[slot * E + k]);
-                        acc.s1[slot] += Y;
-                        acc.s2[slot] = fma(Y, Y, acc.s2[slot]);
-                    }
-                    acc.n += 1;
                 }
             }
+        }
+#pragma unroll
+        for (int slot = 0; slot < NP; ++slot) {
+            acc.s1[slot] += (p1[0][slot] + p1[1][slot]) + (p1[2][slot] + p1[3][slot]);
+            acc.s2[slot] += (p2[0][slot] + p2[1][slot]) + (p2[2][slot] + p2[3][slot]);
         }
     }
 
