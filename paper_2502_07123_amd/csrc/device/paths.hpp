@@ -567,11 +567,12 @@ struct PathBody {
     // cost more than a count.)
     static constexpr bool YTAB = HIST && !FIXED;
 
-    // The level-0 sample of index k for each payoff slot (as a float: the FP32
-    // payoff difference, exact in FP64), written to ytab[slot * entries + k];
-    // returns false if one is not finite (the caller then counts instead).
+    // The level-0 sample of index k for each payoff slot (the FP32 payoff
+    // difference, held in FP64 so that no path converts it), written to
+    // ytab[slot * entries + k]; returns false if one is not finite (the caller then
+    // counts instead).
     __host__ __device__ __forceinline__ static bool ysample(const LevelDev& L, const void* tab,
-                                                            uint32_t k, float* ytab) {
+                                                            uint32_t k, double* ytab) {
         FSide<ExactT> ex;
         FSide<AT> ap;
         XSide ax;
@@ -580,13 +581,13 @@ struct PathBody {
 #pragma unroll
         for (int slot = 0; slot < NP; ++slot) {
             const int p = NP == 1 ? L.payoff_single : slot;
-            float y = 0.0f;
+            double y = 0.0;
             if (NP == 1 || ((L.payoff_mask >> p) & 1u)) {
                 double Ye, Ya, Y;
                 int64_t Yint;
                 sample(L, p, ex, ap, ax, ExactT(0), ExactT(0), Ye, Ya, Yint, Y);
                 ok = ok && __builtin_isfinite(Y);
-                y = static_cast<float>(Y);
+                y = static_cast<double>(static_cast<float>(Y));
             }
             ytab[slot * L.table_entries + k] = y;
         }
@@ -597,7 +598,7 @@ struct PathBody {
     // per-index table; partial groups and debug records take the checked loop.
     __host__ __device__ __forceinline__ static void ytab_group(const LevelDev& L, const WorkDev& W,
                                                                uint64_t g, const void* tab,
-                                                               const float* ytab, Acc<NP>& acc) {
+                                                               const double* ytab, Acc<NP>& acc) {
         const uint64_t path0 = g * WPB;
         const u32x4 r = philox4x32_10(
             u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
@@ -622,7 +623,7 @@ struct PathBody {
                     const int c = (wi * F + fi) & 3;
 #pragma unroll
                     for (int slot = 0; slot < NP; ++slot) {
-                        const double Y = static_cast<double>(ytab[slot * E + k]);
+                        const double Y = ytab[slot * E + k];
                         p1[c][slot] += Y;
                         p2[c][slot] = fma(Y, Y, p2[c][slot]);
                     }
@@ -649,7 +650,7 @@ struct PathBody {
                         }
 #pragma unroll
                         for (int slot = 0; slot < NP; ++slot) {
-                            const double Y = static_cast<double>(ytab[slot * E + k]);
+                            const double Y = ytab[slot * E + k];
                             p1[c][slot] += Y;
                             p2[c][slot] = fma(Y, Y, p2[c][slot]);
                         }

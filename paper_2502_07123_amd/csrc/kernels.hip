@@ -156,7 +156,7 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
             ytab = false;
             if (Body::YTAB && L.level == 0 && uint32_t(NP) * L.table_entries <= YTAB_MAX_ENTRIES) {
                 // per-index samples of this level (after the step table)
-                float* yt = reinterpret_cast<float*>(s_tab + L.table_bytes);
+                double* yt = reinterpret_cast<double*>(s_tab + L.table_bytes);
                 for (uint32_t k = threadIdx.x; k < L.table_entries; k += blockDim.x)
                     if (!Body::ysample(L, s_tab, k, yt)) s_ybad = 1u;
                 __syncthreads();
@@ -167,7 +167,7 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
         acc_zero(acc);
         const uint64_t gend = td.group_begin + td.n_groups;
         if (Body::YTAB && ytab && L.level == 0) {
-            const float* yt = reinterpret_cast<const float*>(s_tab + L.table_bytes);
+            const double* yt = reinterpret_cast<const double*>(s_tab + L.table_bytes);
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::ytab_group(L, W, g, s_tab, yt, acc);
         } else if (Body::HIST && L.level == 0) {

@@ -334,7 +334,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             if (g.v.est == MLMC_EST_APPROX) {
                 extra = 4u * Lw.table_entries;
                 const uint32_t ys = static_cast<uint32_t>(g.v.np) * Lw.table_entries;
-                if (g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) extra = std::max(extra, 4u * ys);
+                if (g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) extra = std::max(extra, 8u * ys);
             }
             g.lds = std::max<uint32_t>(g.lds, Lw.table_bytes + extra);
         }
