@@ -260,11 +260,11 @@ typedef struct mlmc_kernel_stat {
  *                 normals computed ahead by a separate kernel (off the paths'
  *                 sequential chains); 0 disables.
  *   overlap_min_steps: launch sequences of at least this many fine path-steps
- *                 upload their plan on a second (copy) stream while earlier
- *                 sequences compute, and run their approximate-estimator kernels on
- *                 a third stream beside the exact-normal ones; smaller sequences use
- *                 the context's stream alone (each cross-stream dependency costs the
- *                 host ~10 us).  Default 2^26. */
+ *                 run their approximate-estimator kernels, with those works'
+ *                 reduction and download, on a second stream beside the
+ *                 exact-normal ones (each stream uploads its own copy of the plan,
+ *                 so neither waits for the other); smaller sequences use the
+ *                 context's stream alone.  Default 2^26. */
 typedef struct mlmc_tuning {
     uint32_t struct_size;
     uint32_t block_table, block_exact;

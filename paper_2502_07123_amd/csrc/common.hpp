@@ -90,6 +90,39 @@ struct TileDev {
     uint32_t pad;
 };
 
+// The tiles of one work in a path-kernel launch, generated on the device: tile j of
+// the work covers groups [g0 + j per, min(g0 + (j + 1) per, g1)) and writes slot
+// slot_begin + j; the launch numbers tiles consecutively, this work's ending at
+// tile_end (exclusive).
+struct WorkTilesDev {
+    uint64_t g0, g1, per;
+    uint32_t work;
+    uint32_t tile_end;
+    uint32_t slot_begin;
+    uint32_t pad;
+};
+
+// Tile t of a launch from its works' descriptors (binary search on tile_end).
+__host__ __device__ __forceinline__ TileDev tile_of(const WorkTilesDev* wt, uint32_t n_wt, uint32_t t) {
+    uint32_t lo = 0, hi = n_wt - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (wt[mid].tile_end > t) hi = mid;
+        else lo = mid + 1;
+    }
+    const WorkTilesDev w = wt[lo];
+    const uint32_t begin = lo ? wt[lo - 1].tile_end : 0u;
+    const uint64_t j = t - begin;
+    TileDev td;
+    td.work = w.work;
+    td.slot = w.slot_begin + static_cast<uint32_t>(j);
+    td.group_begin = w.g0 + j * w.per;
+    const uint64_t rest = w.g1 - td.group_begin;
+    td.n_groups = static_cast<uint32_t>(rest < w.per ? rest : w.per);
+    td.pad = 0;
+    return td;
+}
+
 // Partial or accumulated sums of one work item (all payoffs).
 struct SlotDev {
     double s1[NPAY], s2[NPAY], e1[NPAY], e2[NPAY];
@@ -101,7 +134,7 @@ struct SlotDev {
 struct ReduceDev {
     uint32_t slot_begin, slot_end;   // this work item's tile slots
     uint32_t kind;                   // sums present: 1 correction, 2 integer, 4 all payoffs
-    uint32_t pad;
+    uint32_t work;                   // its index: the result goes to results[work]
 };
 
 }  // namespace mlmc

@@ -130,9 +130,9 @@ constexpr int max_threads() { return EST == MLMC_EST_APPROX && ARITH != MLMC_ARI
 
 template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, max_threads<EST, ARITH>())))
-k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __restrict__ works,
-        const LevelDev* __restrict__ levels, const uint8_t* __restrict__ tables,
-        SlotDev* __restrict__ slots) {
+k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles,
+        const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
+        const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
     using Body = PathBody<EST, ARITH, MIL, NP, TRACK, F>;
     constexpr bool CORR = EST == MLMC_EST_CORR;
     constexpr bool INTS = ARITH == MLMC_ARITH_FIXED && EST == MLMC_EST_APPROX;
@@ -142,7 +142,7 @@ k_paths(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __re
     uint32_t cur = 0xFFFFFFFFu;
     bool ytab = false;              // level-0 samples of the current level are in LDS
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const TileDev td = tiles[t];
+        const TileDev td = tile_of(wtiles, n_wt, t);
         const WorkDev W = works[td.work];
         const LevelDev& L = levels[W.lvl];
         if (Body::HAS_TABLE && W.lvl != cur) {
@@ -282,7 +282,7 @@ k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, S
     const ReduceDev rd = rds[blockIdx.x];
     const SlotDev* sl = slots + rd.slot_begin;
     const uint32_t ns = rd.slot_end - rd.slot_begin;
-    SlotDev* dst = results + blockIdx.x;
+    SlotDev* dst = results + rd.work;
     switch (rd.kind) {
         case 0: reduce_work<1, false, false>(sl, ns, dst, red); break;
         case 1: reduce_work<1, true, false>(sl, ns, dst, red); break;
@@ -295,7 +295,7 @@ k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, S
 }
 
 // ------------------------------------------------------------------ dispatch
-using PathKernel = void (*)(const TileDev*, uint32_t, const WorkDev*, const LevelDev*,
+using PathKernel = void (*)(const WorkTilesDev*, uint32_t, uint32_t, const WorkDev*, const LevelDev*,
                             const uint8_t*, SlotDev*);
 
 namespace {
@@ -318,11 +318,11 @@ VariantInfo variant_info(const Variant& v) {
 }
 
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,
-                        hipStream_t st, const TileDev* tiles, uint32_t n_tiles,
+                        hipStream_t st, const WorkTilesDev* wtiles, uint32_t n_wt, uint32_t n_tiles,
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
                         SlotDev* slots) {
     const PathKernel k = reinterpret_cast<PathKernel>(vi.fn);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds_bytes, st, tiles, n_tiles, works, levels,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds_bytes, st, wtiles, n_wt, n_tiles, works, levels,
                        tables, slots);
     return hipGetLastError();
 }

@@ -84,8 +84,9 @@ struct VariantInfo {
 
 VariantInfo variant_info(const Variant& v);   // fn == nullptr when not compiled
 
+// n_tiles tiles generated from n_wt work descriptors (tile_of)
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,
-                        hipStream_t st, const TileDev* tiles, uint32_t n_tiles,
+                        hipStream_t st, const WorkTilesDev* wtiles, uint32_t n_wt, uint32_t n_tiles,
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
                         SlotDev* slots);
 
@@ -94,7 +95,8 @@ hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev
                           uint32_t n_tiles, const WorkDev* works, const LevelDev* levels,
                           const uint8_t* tables);
 
-// results[w] = fixed-order sum of work w's tile slots (one block per work)
+// results[rds[b].work] = fixed-order sum of that work's tile slots (block b of n
+// takes rds[b])
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
                          SlotDev* results);
 

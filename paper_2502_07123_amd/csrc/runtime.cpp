@@ -66,7 +66,8 @@ struct LaunchGroup {
     Variant v;
     VariantInfo vi;
     std::vector<uint32_t> works;
-    uint32_t t0 = 0, t1 = 0, block = 0, lds = 0;
+    uint32_t w0 = 0, w1 = 0;        // its work-tile descriptors
+    uint32_t n_tiles = 0, block = 0, lds = 0;
 };
 
 constexpr size_t MAX_FLIGHTS = 4;
@@ -133,10 +134,13 @@ void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
 // Waits for a flight, copies its results (to out, or to the mlmc_sums of its
 // enqueued work list) and returns its staging buffer and events to the pools.
 mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out) {
-    const hipError_t e = hipEventSynchronize(f.done);
+    hipError_t e = hipEventSynchronize(f.done);
     ctx->ev_plain.push_back(f.done);
-    if (f.up) ctx->ev_plain.push_back(f.up);        // completed before the flight's kernels
-    if (f.join) ctx->ev_plain.push_back(f.join);    // completed before its reduction
+    if (f.done_aux) {
+        const hipError_t e2 = hipEventSynchronize(f.done_aux);
+        if (e == hipSuccess) e = e2;
+        ctx->ev_plain.push_back(f.done_aux);
+    }
     PinnedBuf& pb = ctx->pins[f.pin];
     pb.busy = false;
     if (e != hipSuccess) {
@@ -144,6 +148,12 @@ mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out)
         return fail(ctx, MLMC_E_DEVICE, std::string("launch sequence failed: ") + hipGetErrorString(e));
     }
     const SlotDev* res = reinterpret_cast<const SlotDev*>(pb.p + f.down_off);
+    std::vector<SlotDev> by_work;
+    if (!f.order.empty()) {                 // results in stream order: back to work order
+        by_work.resize(f.n_works);
+        for (uint32_t p = 0; p < f.n_works; ++p) by_work[f.order[p]] = res[p];
+        res = by_work.data();
+    }
     if (out) out->assign(res, res + f.n_works);
     if (f.sink) f.sink->assign(res, res + f.n_works);
     for (size_t i = 0; i < f.deliver.size(); ++i) {
@@ -258,7 +268,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     for (auto& kv : groups)
         std::stable_sort(kv.second.works.begin(), kv.second.works.end(),
                          [&](uint32_t a, uint32_t b) { return works[a].level > works[b].level; });
-    std::vector<TileDev> tiles;
+    std::vector<WorkTilesDev> wtiles;
+    uint32_t n_slots = 0;
     std::vector<ReduceDev> reds(works.size());
     // works with few, long paths get their exact normals computed ahead (k_normals)
     std::vector<TileDev> ntiles[2];                 // [0]: FP64 normals, [1]: FP32
@@ -271,7 +282,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         g.block = std::min<uint32_t>(g.vi.tab_bytes && g.v.est == MLMC_EST_APPROX ? ctx->tune.block_table
                                                                                   : ctx->tune.block_exact,
                                      static_cast<uint32_t>(g.vi.max_block));
-        g.t0 = static_cast<uint32_t>(tiles.size());
+        g.w0 = static_cast<uint32_t>(wtiles.size());
         for (uint32_t wi : g.works) {
             const WorkSpec& w = works[wi];
             const uint64_t N = uint64_t(1) << w.level;
@@ -312,21 +323,25 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             uint64_t per = uint64_t(g.block) * ppt;
             const uint64_t max_tiles = 1u << 16;
             if ((total + per - 1) / per > max_tiles) per = (total + max_tiles - 1) / max_tiles;
-            reds[wi].slot_begin = static_cast<uint32_t>(tiles.size());
-            for (uint64_t gg = g0; gg < g1; gg += per) {
-                TileDev t;
-                t.work = wi;
-                t.slot = static_cast<uint32_t>(tiles.size());
-                t.group_begin = gg;
-                t.n_groups = static_cast<uint32_t>(std::min(per, g1 - gg));
-                t.pad = 0;
-                tiles.push_back(t);
-            }
-            reds[wi].slot_end = static_cast<uint32_t>(tiles.size());
+            const uint64_t nt = (total + per - 1) / per;
+            if (uint64_t(n_slots) + nt >= (uint64_t(1) << 31)) return fail(ctx, MLMC_E_NOMEM, "too many tiles");
+            WorkTilesDev wt;
+            wt.g0 = g0;
+            wt.g1 = g1;
+            wt.per = per;
+            wt.work = wi;
+            wt.tile_end = g.n_tiles + static_cast<uint32_t>(nt);
+            wt.slot_begin = n_slots;
+            wt.pad = 0;
+            wtiles.push_back(wt);
+            reds[wi].slot_begin = n_slots;
+            n_slots += static_cast<uint32_t>(nt);
+            g.n_tiles += static_cast<uint32_t>(nt);
+            reds[wi].slot_end = n_slots;
             reds[wi].kind = (g.v.est == MLMC_EST_CORR ? 1u : 0u) |
                             (g.v.est == MLMC_EST_APPROX && g.v.arith == MLMC_ARITH_FIXED ? 2u : 0u) |
                             (g.v.np == NPAY ? 4u : 0u);
-            reds[wi].pad = 0;
+            reds[wi].work = wi;
             // table, plus the level-0 index histogram of the approximate estimator or
             // (FP32, small enough) its per-index sample table
             const LevelDev& Lw = levels[wdev[wi].lvl];
@@ -338,22 +353,56 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             }
             g.lds = std::max<uint32_t>(g.lds, Lw.table_bytes + extra);
         }
-        g.t1 = static_cast<uint32_t>(tiles.size());
+        g.w1 = static_cast<uint32_t>(wtiles.size());
     }
-    if (tiles.size() >= (size_t(1) << 31)) return fail(ctx, MLMC_E_NOMEM, "too many tiles");
+
+    // large flights with both table-only and exact-normal works run the table-only
+    // kernels (and their works' reduction) on the second stream: order the reductions
+    // [table-only works | the others]
+    uint64_t flight_steps = 0;
+    for (const WorkSpec& w : works) flight_steps += w.n << w.level;
+    const bool overlap = flight_steps >= ctx->tune.overlap_min_steps;
+    bool has_table = false, has_exact = false;
+    for (auto& kv : groups) {
+        if (!kv.second.n_tiles) continue;
+        (kv.second.v.est == MLMC_EST_APPROX ? has_table : has_exact) = true;
+    }
+    const bool fork = overlap && has_table && has_exact && ctx->aux_stream;
+    // results are written in this order (position p holds work order[p]), so that
+    // each stream downloads one contiguous part
+    uint32_t n_red_aux = 0;
+    f.order.clear();
+    if (fork) {
+        std::vector<ReduceDev> ordered;
+        ordered.reserve(reds.size());
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t wi = 0; wi < works.size(); ++wi) {
+                const bool tab_only = lvl_var[wdev[wi].lvl].est == MLMC_EST_APPROX;
+                if (tab_only != (pass == 0)) continue;
+                f.order.push_back(static_cast<uint32_t>(wi));
+                ordered.push_back(reds[wi]);
+                ordered.back().work = static_cast<uint32_t>(ordered.size() - 1);
+                n_red_aux += tab_only ? 1u : 0u;
+            }
+        reds.swap(ordered);
+    }
 
     // 3. layout (offsets from the flight's base):
-    //    [results | levels | works | tables | tiles | reds | normal tiles | slots | normals]
+    //    [results | levels | works | tables | work tiles | reds | normal tiles | slots | normals]
     const size_t o_res = 0;
     const size_t o_lvl = align_up(o_res + works.size() * sizeof(SlotDev), 256);
     const size_t o_work = align_up(o_lvl + levels.size() * sizeof(LevelDev), 256);
     const size_t o_tab = align_up(o_work + wdev.size() * sizeof(WorkDev), 256);
     const size_t o_tile = align_up(o_tab + tables.size(), 256);
-    const size_t o_red = align_up(o_tile + tiles.size() * sizeof(TileDev), 256);
+    const size_t o_red = align_up(o_tile + wtiles.size() * sizeof(WorkTilesDev), 256);
     const size_t o_nt0 = align_up(o_red + reds.size() * sizeof(ReduceDev), 256);
     const size_t o_nt1 = align_up(o_nt0 + ntiles[0].size() * sizeof(TileDev), 256);
-    const size_t o_slot = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
-    size_t o_zb = align_up(o_slot + tiles.size() * sizeof(SlotDev), 256);
+    const size_t o_end_plan = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
+    // the second stream reads its own copy of the plan (uploaded on that stream, so
+    // neither stream waits for the other)
+    const size_t o_copy = o_end_plan;
+    const size_t o_slot = fork ? align_up(o_copy + (o_end_plan - o_lvl), 256) : o_end_plan;
+    size_t o_zb = align_up(o_slot + size_t(n_slots) * sizeof(SlotDev), 256);
     std::vector<size_t> zb_off(works.size(), 0);
     for (size_t i = 0; i < works.size(); ++i) {
         if (zb_f32[i] < 0) continue;
@@ -393,8 +442,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         wdev[i].zbuf = reinterpret_cast<uint64_t>(d + zb_off[i] + align_up(pos * 4, 256));
     }
 
-    // 5. stage and upload [levels .. slots), launch, download the results
-    const size_t up_bytes = o_slot - o_lvl;
+    // 5. stage and upload [levels .. normal tiles], launch, download the results
+    const size_t up_bytes = o_end_plan - o_lvl;
     const size_t down_bytes = works.size() * sizeof(SlotDev);
     f.down_off = align_up(up_bytes, 256);
     mlmc_status st = take_pinned(ctx, f.down_off + down_bytes, f.pin);
@@ -408,33 +457,16 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     std::memcpy(h + (o_lvl - o_lvl), levels.data(), levels.size() * sizeof(LevelDev));
     std::memcpy(h + (o_work - o_lvl), wdev.data(), wdev.size() * sizeof(WorkDev));
     if (!tables.empty()) std::memcpy(h + (o_tab - o_lvl), tables.data(), tables.size());
-    std::memcpy(h + (o_tile - o_lvl), tiles.data(), tiles.size() * sizeof(TileDev));
+    std::memcpy(h + (o_tile - o_lvl), wtiles.data(), wtiles.size() * sizeof(WorkTilesDev));
     std::memcpy(h + (o_red - o_lvl), reds.data(), reds.size() * sizeof(ReduceDev));
     if (!ntiles[0].empty()) std::memcpy(h + (o_nt0 - o_lvl), ntiles[0].data(), ntiles[0].size() * sizeof(TileDev));
     if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
     hipStream_t s = ctx->stream;
-    uint64_t flight_steps = 0;
-    for (const WorkSpec& w : works) flight_steps += w.n << w.level;
-    const bool overlap = flight_steps >= ctx->tune.overlap_min_steps;
-    // large flights: the plan goes up on the context's copy stream, so it overlaps the
-    // kernels of the flights still running (its ring region and staging buffer are its
-    // own); the kernels wait for it through an event
-    hipError_t ue = hipSuccess;
-    if (overlap) {
-        if ((st = take_event(ctx, false, f.up)) != MLMC_OK) {
-            release();
-            return st;
-        }
-        ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, ctx->copy_stream);
-        if (ue == hipSuccess) ue = hipEventRecord(f.up, ctx->copy_stream);
-        if (ue == hipSuccess) ue = hipStreamWaitEvent(s, f.up, 0);
-    } else {
-        ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s);
-    }
+    hipStream_t sa = fork ? ctx->aux_stream : s;
+    hipError_t ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s);
+    if (ue == hipSuccess && fork) ue = hipMemcpyAsync(d + o_copy, h, up_bytes, hipMemcpyHostToDevice, sa);
     if (ue != hipSuccess) {
         release();
-        if (f.up) ctx->ev_plain.push_back(f.up);
-        f.up = nullptr;
         return fail(ctx, MLMC_E_DEVICE, std::string("upload: ") + hipGetErrorString(ue));
     }
     launched = true;                      // from here the staging buffer belongs to the flight
@@ -442,6 +474,9 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     f.end = base + total;
     f.n_works = static_cast<uint32_t>(works.size());
     if ((st = take_event(ctx, false, f.done)) != MLMC_OK) return st;
+    if (fork && (st = take_event(ctx, false, f.done_aux)) != MLMC_OK) return st;
+    // the second stream's copy of the plan
+    uint8_t* da = fork ? d + (o_copy - o_lvl) : d;
     // exact normals ahead of the path kernels for the buffered works
     const uint32_t ngrid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * 4;
     for (int k = 0; k < 2; ++k) {
@@ -454,21 +489,16 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     }
     // path kernels, one per variant, then the fixed-order reduction of each work.
     // Table-only (approximate) groups do not wait for the normals-ahead kernel: when a
-    // flight has both kinds they run on the context's second stream, concurrently with
-    // the exact-normal groups, and join before the reduction.
+    // large flight has both kinds they run on the context's second stream, reading
+    // that stream's copy of the plan, concurrently with the exact-normal groups.
     const uint32_t max_grid = static_cast<uint32_t>(std::max(1, ctx->cu_count)) * ctx->tune.blocks_per_cu;
-    bool has_table = false, has_exact = false;
-    for (auto& kv : groups) {
-        if (kv.second.t1 == kv.second.t0) continue;
-        (kv.second.v.est == MLMC_EST_APPROX ? has_table : has_exact) = true;
-    }
-    const bool fork = overlap && has_table && has_exact && ctx->aux_stream;
-    if (fork) HIPCHK(hipStreamWaitEvent(ctx->aux_stream, f.up, 0));
     for (auto& kv : groups) {
         LaunchGroup& g = kv.second;
-        const uint32_t nt = g.t1 - g.t0;
+        const uint32_t nt = g.n_tiles;
         if (!nt) continue;
-        hipStream_t gs = (fork && g.v.est == MLMC_EST_APPROX) ? ctx->aux_stream : s;
+        const bool on_aux = fork && g.v.est == MLMC_EST_APPROX;
+        hipStream_t gs = on_aux ? sa : s;
+        uint8_t* dp = on_aux ? da : d;           // plan copy of that stream
         const uint32_t grid = std::min(nt, max_grid);
         Flight::Timed tm{};
         if (ctx->timing) {
@@ -480,20 +510,30 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             HIPCHK(hipEventRecord(tm.e0, gs));
         }
         HIPCHK(launch_paths(g.vi, grid, g.block, g.lds, gs,
-                            reinterpret_cast<const TileDev*>(d + o_tile) + g.t0, nt,
-                            reinterpret_cast<const WorkDev*>(d + o_work),
-                            reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab,
+                            reinterpret_cast<const WorkTilesDev*>(dp + o_tile) + g.w0, g.w1 - g.w0, nt,
+                            reinterpret_cast<const WorkDev*>(dp + o_work),
+                            reinterpret_cast<const LevelDev*>(dp + o_lvl), dp + o_tab,
                             reinterpret_cast<SlotDev*>(d + o_slot)));
         if (ctx->timing) HIPCHK(hipEventRecord(tm.e1, gs));
     }
+    const SlotDev* sl_dev = reinterpret_cast<const SlotDev*>(d + o_slot);
+    SlotDev* res_dev = reinterpret_cast<SlotDev*>(d + o_res);
     if (fork) {
-        if ((st = take_event(ctx, false, f.join)) != MLMC_OK) return st;
-        HIPCHK(hipEventRecord(f.join, ctx->aux_stream));
-        HIPCHK(hipStreamWaitEvent(s, f.join, 0));
+        // each stream reduces and downloads its own works' results (positions
+        // [0, n_red_aux) on the second stream) and records its own completion event
+        const size_t sz = sizeof(SlotDev);
+        HIPCHK(launch_reduce(n_red_aux, sa, sl_dev, reinterpret_cast<const ReduceDev*>(da + o_red), res_dev));
+        HIPCHK(hipMemcpyAsync(h + f.down_off, d + o_res, n_red_aux * sz, hipMemcpyDeviceToHost, sa));
+        HIPCHK(hipEventRecord(f.done_aux, sa));
+        HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()) - n_red_aux, s, sl_dev,
+                             reinterpret_cast<const ReduceDev*>(d + o_red) + n_red_aux, res_dev));
+        HIPCHK(hipMemcpyAsync(h + f.down_off + n_red_aux * sz, d + o_res + n_red_aux * sz,
+                              down_bytes - n_red_aux * sz, hipMemcpyDeviceToHost, s));
+    } else {
+        HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s, sl_dev,
+                             reinterpret_cast<const ReduceDev*>(d + o_red), res_dev));
+        HIPCHK(hipMemcpyAsync(h + f.down_off, d + o_res, down_bytes, hipMemcpyDeviceToHost, s));
     }
-    HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s, reinterpret_cast<const SlotDev*>(d + o_slot),
-                         reinterpret_cast<const ReduceDev*>(d + o_red), reinterpret_cast<SlotDev*>(d + o_res)));
-    HIPCHK(hipMemcpyAsync(h + f.down_off, d + o_res, down_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(f.done, s));
     return MLMC_OK;
 }
@@ -870,17 +910,11 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
     ctx->ws_bytes = workspace_bytes;
-    if (hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete ctx;
-        return MLMC_E_DEVICE;
-    }
     if (hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipStreamDestroy(ctx->copy_stream);
         delete ctx;
         return MLMC_E_DEVICE;
     }
     if (hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
-        (void)hipStreamDestroy(ctx->copy_stream);
         (void)hipStreamDestroy(ctx->aux_stream);
         delete ctx;
         return MLMC_E_DEVICE;
@@ -889,7 +923,6 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
         ctx->ws = static_cast<uint8_t*>(workspace);
     } else {
         if (hipMalloc(reinterpret_cast<void**>(&ctx->ws), workspace_bytes) != hipSuccess) {
-            (void)hipStreamDestroy(ctx->copy_stream);
             (void)hipStreamDestroy(ctx->aux_stream);
             delete ctx;
             return MLMC_E_NOMEM;
@@ -907,11 +940,9 @@ void mlmc_context_destroy(mlmc_context* ctx) {
         std::lock_guard<std::mutex> lock(ctx->dev_mtx);
         (void)drain_flights(ctx);
     }
-    if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
     if (ctx->aux_stream) (void)hipStreamSynchronize(ctx->aux_stream);
     for (hipEvent_t e : ctx->ev_plain) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_timed) (void)hipEventDestroy(e);
-    if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     for (auto& pb : ctx->pins)
         if (pb.p) (void)hipHostFree(pb.p);

@@ -33,9 +33,9 @@ struct Tuning {
     // stream positions) get their normals computed ahead, off the paths' chains
     uint64_t zb_max_paths = 1u << 15;
     uint64_t zb_max_positions = 1u << 22;
-    // flights of at least this many fine path-steps upload on the copy stream and run
-    // their table-only kernels on the second stream (each cross-stream wait costs the
-    // host about 10 us, which small flights do not win back)
+    // flights of at least this many fine path-steps run their table-only kernels on
+    // the second stream (a second plan upload and a second download, which small
+    // flights do not win back)
     uint64_t overlap_min_steps = uint64_t(1) << 26;
 };
 
@@ -70,8 +70,8 @@ struct Flight {
     size_t down_off = 0;
     uint32_t n_works = 0;
     hipEvent_t done = nullptr;
-    hipEvent_t up = nullptr;        // the plan's upload (on the context's copy stream)
-    hipEvent_t join = nullptr;      // table-only kernels done on the second stream
+    hipEvent_t done_aux = nullptr;  // the second stream's part (two-stream flights)
+    std::vector<uint32_t> order;    // two-stream flights: result position -> work
     struct Timed {
         Variant v;
         uint64_t steps = 0;
@@ -88,7 +88,6 @@ struct Flight {
 struct mlmc_context {
     int device = 0;
     hipStream_t stream = nullptr;
-    hipStream_t copy_stream = nullptr;   // plan uploads (default priority, non-blocking)
     hipStream_t aux_stream = nullptr;    // table-only path kernels beside the exact-normal ones
     bool own_ws = false;
     uint8_t* ws = nullptr;
