@@ -288,3 +288,47 @@ def test_autotune_keeps_results_valid():
                     assert abs(a[p][k2] - z[p][k2]) <= tol2, (i, p, k2)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("how", ["sync", "enqueued", "estimate", "server"])
+def test_two_stream_flights_equal_one_stream(how):
+    """Flights that put the approximate works on the second stream (each stream with
+    its own plan copy, reduction and download, results returned in work order) give
+    the same sums as one-stream flights: synchronous batches, several enqueued
+    batches in flight, and an adaptive estimate."""
+    c = M.Context(0, workspace_bytes=256 << 20)
+    try:
+        items = _items()
+        runs = []
+        for thr in ((1 << 64) - 1, 0):
+            c.set_tuning(overlap_min_steps=thr)
+            if how == "sync":
+                runs.append(c.level_sums_batch(items))
+            elif how == "enqueued":
+                bs = [c.sums_batch(_items(off=1000 * k)) for k in range(3)]
+                for b in bs:
+                    b.enqueue()
+                out = []
+                for b in bs:
+                    b.wait()
+                    out.append(b.as_dicts())
+                runs.append(out)
+            elif how == "estimate":
+                cfg, _, _ = _configs(True, "milstein", "fp32", eps=0.003)
+                runs.append([c.estimate(p, cfg, SEED, option=i) for i, p in enumerate(_strikes())])
+            else:
+                cfg, _, _ = _configs(True, "milstein", "fp32", eps=0.003)
+                c.server_start(cfg, max_active=8)
+                try:
+                    tickets = [c.submit(p, 0.003, SEED, option=i) for i, p in enumerate(_strikes())]
+                    got = _collect(c, tickets)
+                finally:
+                    c.server_stop()
+                runs.append([got[t] for t in tickets])
+        if how in ("estimate", "server"):
+            for r in runs:
+                for x in r:
+                    x.pop("seconds")                # wall time, not a result
+        assert runs[0] == runs[1]
+    finally:
+        c.close()
