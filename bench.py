@@ -258,9 +258,14 @@ def main():
                            "path_steps_per_step": per_step_steps,
                            "alg_lane_ops_per_step": ops}}
 
+    bs = closed_form(dict(GBM, kind="euro"))
+    last = ests[-1][0]
     extra = {
         "estimate": float(np.mean([e[0] for e in ests])),
         "rmse_bound": float(ests[-1][1]),
+        # one step's estimate against the Black-Scholes price (discretisation bias of
+        # levels 0..8 plus sampling error; the step's RMSE target is eps)
+        "closed_form": bs, "step_error": last - bs, "step_error_over_eps": (last - bs) / EPS,
         "N_approx": [int(x) for x in Na], "N_corr": [int(x) for x in Nc],
         "tuning": tuning,
         "kernels": [{"estimator": s["estimator"], "arith": s["arith"], "fields": s["fields"],
@@ -317,8 +322,10 @@ def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p):
             r = ctx.estimate(prob, cfg, SEED + 2 + rep)
             ts.append(time.perf_counter() - t0)
             ests.append(r["estimate"])
+        bs = closed_form(dict(GBM, kind="euro"))
         out[name] = {"seconds": float(np.median(ts)), "estimate": float(np.mean(ests)),
-                     "rmse_bound": math.sqrt(r["variance"]), "path_steps": r["path_steps"]}
+                     "rmse_bound": math.sqrt(r["variance"]), "path_steps": r["path_steps"],
+                     "errors_vs_closed_form": [float(e - bs) for e in ests]}
     out["speedup"] = out["plain_fp32"]["seconds"] / out["nested"]["seconds"]
     out["cost_ns_per_step"] = {"plain_fp32": c_p, "approx": c_a, "corr": c_c}
     return out
