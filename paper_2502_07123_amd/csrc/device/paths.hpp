@@ -131,6 +131,24 @@ __host__ __device__ __forceinline__ T multiplier_lp(T z, T con1, T con2, T con3,
     return s;
 }
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// FP16 on the device: the coarse step's independent operation pairs as packed math,
+// (mul1, zsq) = (con2, zs) * (zs, zs) and (sum1, zm1) = (con1, -c) + (mul1, zsq), each
+// lane rounded as the scalar operation (IEEE, per element), so the result equals
+// multiplier_lp<MIL, _Float16> bit for bit.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+template <bool MIL>
+__device__ __forceinline__ _Float16 multiplier_h2(_Float16 z, _Float16 con1, _Float16 con2, _Float16 con3,
+                                                  _Float16 c) {
+#pragma clang fp contract(off)
+    if (!MIL) return con1 + con2 * z;
+    const half2v p = half2v{con2, z} * half2v{z, z};            // v_pk_mul_f16
+    const half2v q = half2v{con1, -c} + p;                      // v_pk_add_f16
+    const _Float16 mul3 = con3 * q.y;
+    return q.x + mul3;
+}
+#endif
+
 template <typename T>
 __host__ __device__ __forceinline__ T advance_lp(T x, T s) {
 #pragma clang fp contract(off)
@@ -197,7 +215,12 @@ __host__ __device__ __forceinline__ void table_step(FSide<T>& s, T z, T sk, cons
 #pragma clang fp contract(off)
             const LpConst<T> c = lp_const<T>(L);
             const T zs = s.zp + z;
-            s.xc = advance_lp<T>(s.xc, multiplier_lp<MIL, T>(zs, c.con1c, c.con2, c.con3, T(2)));
+#if defined(__HIP_DEVICE_COMPILE__)
+            if constexpr (std::is_same<T, _Float16>::value)
+                s.xc = advance_lp<T>(s.xc, multiplier_h2<MIL>(zs, c.con1c, c.con2, c.con3, T(2)));
+            else
+#endif
+                s.xc = advance_lp<T>(s.xc, multiplier_lp<MIL, T>(zs, c.con1c, c.con2, c.con3, T(2)));
             s.track_c(track);
         }
     }
