@@ -153,13 +153,15 @@ def main():
                     help="instead: Poisson-arrival serving, p50/p99 latency (nested vs plain FP32)")
     ap.add_argument("--serve-rates", default="1000,5000,20000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--per-level", action="store_true",
+                    help="instead: path-steps/s per level for each kernel class")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
-    if args.batch or args.serving:
+    if args.batch or args.serving or args.per_level:
         return main_workloads(args)
     import numpy as np
     import torch
@@ -514,6 +516,38 @@ def batch(M, ctx, costs, eps_list, n_opt=256):
     return out
 
 
+def per_level(M, ctx, steps_per_work=1 << 27, reps=3):
+    """Path-steps/s of one level's work by kernel class and level (HIP events around
+    the path kernels of a one-work launch, about 1.3e8 fine path-steps per work)."""
+    prob = M.make_problem("milstein", ("euro",), **GBM)
+    fixed = M.make_precision("fixed", 8, False, {
+        "X": (32, 22), "con1": (32, 34), "con2": (32, 33), "con3": (32, 36), "Z": (31, 28),
+        "mul1": (32, 30), "sum1": (32, 30), "zsq": (32, 23), "zm1": (32, 23), "mul3": (32, 29),
+        "sum2": (32, 29), "mul2": (32, 27)})
+    modes = [("approx_fp32_q8_packed", M.make_precision("fp32", 8, True), M.EST_APPROX),
+             ("approx_fp16_q8_packed", M.make_precision("fp16", 8, True), M.EST_APPROX),
+             ("approx_fixed_q8", fixed, M.EST_APPROX),
+             ("corr_fp32_q8", M.make_precision("fp32", 8), M.EST_CORR),
+             ("plain_fp32", M.make_precision("fp32", 8), M.EST_PLAIN),
+             ("plain_fp64", M.make_precision("fp64", 8), M.EST_PLAIN)]
+    out = []
+    for name, prec, est in modes:
+        row = {"mode": name}
+        for l in range(0, 11):
+            n = max(steps_per_work >> l, 4096)
+            ctx.level_sums(prob, l, n, 0, prec, est, SEED)            # warm
+            ctx.set_timing(True)
+            for r in range(reps):
+                ctx.level_sums(prob, l, n, n * (r + 1), prec, est, SEED)
+            st = ctx.kernel_stats()
+            ctx.set_timing(False)
+            ms = sum(x["ms"] for x in st) / reps
+            row[str(l)] = (n << l) / (ms * 1e-3)
+        out.append(row)
+        print(json.dumps({"per_level": row}), file=sys.stderr, flush=True)
+    return out
+
+
 def main_workloads(args):
     """--batch / --serving: one JSON line with the batched and/or served workloads."""
     import torch
@@ -529,6 +563,8 @@ def main_workloads(args):
     if args.serving:
         line["serving"] = serving(M, ctx, costs, [float(x) for x in args.serve_rates.split(",")],
                                   args.serve_seconds)
+    if args.per_level:
+        line["per_level_path_steps_per_s"] = per_level(M, ctx)
     torch.cuda.synchronize()
     print(json.dumps(line))
     ctx.close()
