@@ -29,9 +29,13 @@ __host__ __device__ __forceinline__ int64_t fx_saturate(int64_t v, int32_t w, ui
     return v > hi ? hi : (v < lo ? lo : v);
 }
 
+// Both factors of every product of the path are saturated variables, table entries or
+// quantised constants of at most 32 bits (and Zs = Z + Z' with Z of at most 31 bits),
+// so the product is a 32 x 32 -> 64-bit signed multiply.
 __host__ __device__ __forceinline__ int64_t fx_mul(int64_t a, int64_t b, const FxOp& op,
                                                    uint32_t& nsat) {
-    return fx_saturate(fx_round_shift(a * b, op.s), op.w, nsat);
+    const int64_t p = static_cast<int64_t>(static_cast<int32_t>(a)) * static_cast<int32_t>(b);
+    return fx_saturate(fx_round_shift(p, op.s), op.w, nsat);
 }
 
 __host__ __device__ __forceinline__ int64_t fx_add(int64_t a, int64_t b, const FxOp& op,
