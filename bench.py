@@ -76,7 +76,7 @@ KERNEL_SOURCES = ("paper_2502_07123_amd/csrc/kernels.hip", "paper_2502_07123_amd
                   "paper_2502_07123_amd/csrc/common.hpp", "paper_2502_07123_amd/csrc/device/paths.hpp",
                   "paper_2502_07123_amd/csrc/device/philox.hpp", "paper_2502_07123_amd/csrc/device/norminv.hpp",
                   "paper_2502_07123_amd/csrc/device/fixed.hpp")
-TRAFFIC_RECORD = "profiles/k_paths_approx_cfg2_hbm_traffic.md"
+TRAFFIC_RECORD = "profiles/k_paths_approx_milstein_euro_L0_8_hbm_traffic.md"
 
 
 def kernel_source_hash():
@@ -112,6 +112,13 @@ def combine_np(S, scale):
     m = s["sum1"] / n
     v = np.maximum((s["sum2"] - s["sum1"] ** 2 / n) / (n - 1.0), 0.0)
     return scale * float(m.sum()), scale * math.sqrt(float((v / n).sum()))
+
+
+def level_mean(S, l, scale):
+    """Mean of the level-l correction E[Y_l] (approximate + correction estimator) of a
+    batch laid out as make_items lays it out, in price units."""
+    s = S[:, 0]
+    return scale * float(s["sum1"][2 * l] / s["n"][2 * l] + s["sum1"][2 * l + 1] / s["n"][2 * l + 1])
 
 
 def cpu_baseline(Na, Nc, budget_paths_steps=1.5e8):
@@ -153,6 +160,8 @@ def main():
                     help="instead: Poisson-arrival serving, p50/p99 latency (nested vs plain FP32)")
     ap.add_argument("--serve-rates", default="1000,5000,20000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--tuning", default=None,
+                    help="launch geometry as JSON (fields of mlmc_tuning) in place of the tuner")
     ap.add_argument("--per-level", action="store_true",
                     help="instead: path-steps/s per level for each kernel class")
     args = ap.parse_args()
@@ -201,30 +210,44 @@ def main():
     # two marshalled batches alternate so that the host prepares step k + 1 while the
     # GPU runs step k; each step draws fresh paths (path offsets advance)
     batches = [ctx.sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, 0)) for _ in range(2)]
-    # launch geometry for this work list by the library's tuner (untimed)
-    tuning = ctx.autotune(batches[0], reps=5)
+    # launch geometry for this work list by the library's tuner (untimed), or the one
+    # given (profiled runs: the tuner's timings are not those of an unprofiled run)
+    if args.tuning:
+        ctx.set_tuning(**json.loads(args.tuning))
+        tuning = ctx.get_tuning()
+    else:
+        tuning = ctx.autotune(batches[0], reps=5)
     off = N_PILOT
-    ests = []
+    ests, top = [], []
+
+    host = {"enqueue_s": 0.0, "wait_s": 0.0}
 
     def run_steps(k_steps, record):
         nonlocal off
         for k in range(k_steps):
             b = batches[k % 2]
             if b._pending is not None:
+                t1 = time.perf_counter()
                 b.wait()
+                host["wait_s"] += time.perf_counter() - t1
                 if record:
                     ests.append(combine_np(b.sums, scale))
+                    top.append(level_mean(b.sums, LEVELS - 1, scale))
             b.offsets[:] = off
             off += int(max(N))
+            t1 = time.perf_counter()
             b.enqueue()
+            host["enqueue_s"] += time.perf_counter() - t1
         for k in range(k_steps, k_steps + 2):
             b = batches[k % 2]
             if b._pending is not None:
                 b.wait()
                 if record:
                     ests.append(combine_np(b.sums, scale))
+                    top.append(level_mean(b.sums, LEVELS - 1, scale))
 
     run_steps(args.warmup, False)
+    host.update(enqueue_s=0.0, wait_s=0.0)
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -262,14 +285,21 @@ def main():
 
     bs = closed_form(dict(GBM, kind="euro"))
     last = ests[-1][0]
+    bias = -float(np.mean(top))
     extra = {
         "estimate": float(np.mean([e[0] for e in ests])),
         "rmse_bound": float(ests[-1][1]),
         # one step's estimate against the Black-Scholes price (discretisation bias of
         # levels 0..8 plus sampling error; the step's RMSE target is eps)
         "closed_form": bs, "step_error": last - bs, "step_error_over_eps": (last - bs) / EPS,
+        # the finest level's bias, -sum_{l>L} E[Y_l] ~ -E[Y_L] at weak order 1, from the
+        # timed steps' level-L means; the step error less it is the sampling error
+        "bias_estimate": bias, "step_error_less_bias": last - bs - bias,
         "N_approx": [int(x) for x in Na], "N_corr": [int(x) for x in Nc],
         "tuning": tuning,
+        # host time per timed step in the library's enqueue (planning, copies, launches)
+        # and in the wait for the step two back (the GPU still busy)
+        "host_us_per_step": {k[:-2]: v * 1e6 / args.steps for k, v in host.items()},
         "kernels": [{"estimator": s["estimator"], "arith": s["arith"], "fields": s["fields"],
                      "launches": s["launches"], "ms": s["ms"],
                      "path_steps_per_s": s["path_steps"] / (s["ms"] * 1e-3)} for s in stats],
@@ -310,7 +340,9 @@ def calibrate(M, ctx, prob, prec_a, prec_c, level=4, n=1 << 22):
 def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p):
     """Wall time of one on-line MLMC estimate to RMSE eps (price units), levels 0..8,
     nested (FP32 table + FP64 correction) vs plain FP32 (exact FP32 normals); the
-    cost model uses the calibrated ns per path-step of each kernel class."""
+    cost model uses the calibrated ns per path-step of each kernel class.  theta = 1
+    gives the whole budget to the sampling variance at the fixed finest level, so the
+    errors against Black-Scholes also hold that level's bias (bias_estimate)."""
     import numpy as np
     out = {}
     for name, nested in (("nested", True), ("plain_fp32", False)):

@@ -294,6 +294,16 @@ k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, S
     }
 }
 
+// A flight's plan from the pinned staging buffer (coherent host memory, mapped into
+// the device's address space) to device memory.  A kernel on the flight's own stream
+// rather than a copy-engine transfer, so the launches behind it are ordered by that
+// stream alone; system-scope loads never see a stale cached line of a reused buffer.
+__global__ void __launch_bounds__(UPLOAD_THREADS)
+k_upload(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, uint32_t n) {
+    const uint32_t i = blockIdx.x * UPLOAD_THREADS + threadIdx.x;
+    if (i < n) dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ------------------------------------------------------------------ dispatch
 using PathKernel = void (*)(const WorkTilesDev*, uint32_t, uint32_t, const WorkDev*, const LevelDev*,
                             const uint8_t*, SlotDev*);
@@ -336,6 +346,15 @@ hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev
     return hipGetLastError();
 }
 
+
+hipError_t launch_upload(const void* host_src, void* dst, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 8 != 0 || bytes / 8 > 0xffffffffull) return hipErrorInvalidValue;
+    const uint32_t n = static_cast<uint32_t>(bytes / 8);
+    hipLaunchKernelGGL(k_upload, dim3((n + UPLOAD_THREADS - 1) / UPLOAD_THREADS), dim3(UPLOAD_THREADS), 0, st,
+                       static_cast<const uint64_t*>(host_src), static_cast<uint64_t*>(dst), n);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
                          SlotDev* results) {

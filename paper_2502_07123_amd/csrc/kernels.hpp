@@ -95,6 +95,11 @@ hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev
                           uint32_t n_tiles, const WorkDev* works, const LevelDev* levels,
                           const uint8_t* tables);
 
+// copies `bytes` (a multiple of 8) from coherent pinned host memory to device memory
+// with a kernel on `st`
+constexpr uint32_t UPLOAD_THREADS = 256;
+hipError_t launch_upload(const void* host_src, void* dst, size_t bytes, hipStream_t st);
+
 // results[rds[b].work] = fixed-order sum of that work's tile slots (block b of n
 // takes rds[b])
 hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,

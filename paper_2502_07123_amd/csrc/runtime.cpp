@@ -89,7 +89,8 @@ mlmc_status take_pinned(mlmc_context* ctx, size_t bytes, int& idx) {
         pb.p = nullptr;
         pb.bytes = 0;
         const size_t want = std::max<size_t>(bytes, size_t(1) << 20);
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pb.p), want, hipHostMallocDefault));
+        // coherent: the flight's upload kernel reads the plan from it directly
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pb.p), want, hipHostMallocCoherent));
         pb.bytes = want;
     }
     ctx->pins[idx].busy = true;
@@ -463,8 +464,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
     hipStream_t s = ctx->stream;
     hipStream_t sa = fork ? ctx->aux_stream : s;
-    hipError_t ue = hipMemcpyAsync(d + o_lvl, h, up_bytes, hipMemcpyHostToDevice, s);
-    if (ue == hipSuccess && fork) ue = hipMemcpyAsync(d + o_copy, h, up_bytes, hipMemcpyHostToDevice, sa);
+    hipError_t ue = launch_upload(h, d + o_lvl, up_bytes, s);
+    if (ue == hipSuccess && fork) ue = launch_upload(h, d + o_copy, up_bytes, sa);
     if (ue != hipSuccess) {
         release();
         return fail(ctx, MLMC_E_DEVICE, std::string("upload: ") + hipGetErrorString(ue));
