@@ -160,11 +160,15 @@ def main():
                     help="instead: Poisson-arrival serving, p50/p99 latency (nested vs plain FP32)")
     ap.add_argument("--serve-rates", default="1000,5000,20000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--depth", type=int, default=2,
+                    help="steps in flight: marshalled batches that alternate (1..4)")
     ap.add_argument("--tuning", default=None,
                     help="launch geometry as JSON (fields of mlmc_tuning) in place of the tuner")
     ap.add_argument("--per-level", action="store_true",
                     help="instead: path-steps/s per level for each kernel class")
     args = ap.parse_args()
+    if not 1 <= args.depth <= 4:
+        ap.error("--depth must be 1..4")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
@@ -209,7 +213,7 @@ def main():
 
     # two marshalled batches alternate so that the host prepares step k + 1 while the
     # GPU runs step k; each step draws fresh paths (path offsets advance)
-    batches = [ctx.sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, 0)) for _ in range(2)]
+    batches = [ctx.sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, 0)) for _ in range(args.depth)]
     # launch geometry for this work list by the library's tuner (untimed), or the one
     # given (profiled runs: the tuner's timings are not those of an unprofiled run)
     if args.tuning:
@@ -225,7 +229,7 @@ def main():
     def run_steps(k_steps, record):
         nonlocal off
         for k in range(k_steps):
-            b = batches[k % 2]
+            b = batches[k % args.depth]
             if b._pending is not None:
                 t1 = time.perf_counter()
                 b.wait()
@@ -238,8 +242,8 @@ def main():
             t1 = time.perf_counter()
             b.enqueue()
             host["enqueue_s"] += time.perf_counter() - t1
-        for k in range(k_steps, k_steps + 2):
-            b = batches[k % 2]
+        for k in range(k_steps, k_steps + args.depth):
+            b = batches[k % args.depth]
             if b._pending is not None:
                 b.wait()
                 if record:
@@ -305,7 +309,7 @@ def main():
                      "path_steps_per_s": s["path_steps"] / (s["ms"] * 1e-3)} for s in stats],
     }
     if not args.no_tte:
-        extra["time_to_eps"] = time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p)
+        extra["time_to_eps"] = time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale)
     cpu = None if args.no_cpu else cpu_baseline(Na, Nc)
     line = {
         "metric": "path-steps/s per level; time to RMSE eps, nested low-prec vs plain FP32",
@@ -337,30 +341,65 @@ def calibrate(M, ctx, prob, prec_a, prec_c, level=4, n=1 << 22):
     return tuple(out)
 
 
-def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p):
+TTE_SEEDS = 32
+# 2.5% and 97.5% quantiles of chi-square with 32 degrees of freedom: the 95% interval
+# of the true RMSE is rmse * sqrt(32 / q) for q in (CHI2_HI, CHI2_LO)
+CHI2_LO, CHI2_HI = 18.291, 49.480
+
+
+def level_reference(M, ctx, prob, scale):
+    """E[P_L] of the finest level L = LEVELS - 1 in price units: the Black-Scholes
+    price less the discrete-time corrections above L, sum_{l>L} E[Y_l], from plain
+    FP64 level sums at L+1 .. L+6 (2^16 paths at L+1, halving per level) plus
+    E[Y_{L+6}] once more for the tail (weak order 1).  Returns (value, std error)."""
+    prec = M.make_precision("fp64", Q)
+    lv = list(range(LEVELS, LEVELS + 6))
+    res = ctx.level_sums_batch([(prob, l, (1 << 16) >> i, 0, prec, M.EST_PLAIN, SEED + 77, 0)
+                                for i, l in enumerate(lv)])
+    m = v = 0.0
+    for i, r in enumerate(res):
+        s = r["euro"]
+        n = s["n"]
+        w = 2.0 if i == len(lv) - 1 else 1.0
+        m += w * s["sum1"] / n
+        v += w * w * max((s["sum2"] - s["sum1"] ** 2 / n) / (n - 1), 0.0) / n
+    return closed_form(dict(GBM, kind="euro")) - scale * m, scale * math.sqrt(v)
+
+
+def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale):
     """Wall time of one on-line MLMC estimate to RMSE eps (price units), levels 0..8,
     nested (FP32 table + FP64 correction) vs plain FP32 (exact FP32 normals); the
     cost model uses the calibrated ns per path-step of each kernel class.  theta = 1
-    gives the whole budget to the sampling variance at the fixed finest level, so the
-    errors against Black-Scholes also hold that level's bias (bias_estimate)."""
+    gives the whole budget to the sampling variance at the fixed finest level L
+    (variance eps^2), so the RMSE over TTE_SEEDS seeds is taken about E[P_L] (the
+    level-L reference); the error against Black-Scholes also holds the level-L bias."""
     import numpy as np
-    out = {}
+    ref, ref_se = level_reference(M, ctx, prob, scale)
+    bs = closed_form(dict(GBM, kind="euro"))
+    out = {"reference_level_L": ref, "reference_se": ref_se, "closed_form": bs, "seeds": TTE_SEEDS}
     for name, nested in (("nested", True), ("plain_fp32", False)):
         cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", theta=1.0, L_min=8, L_max=8,
                                 n_pilot=20_000, costs=(c_p, c_a, c_c), plain_arith="fp32",
                                 prec=prec_a)
         ctx.estimate(prob, cfg, SEED + 1)                  # warm (tables, caches)
-        ts, ests = [], []
-        for rep in range(3):
+        ts, ests, steps = [], [], []
+        for rep in range(TTE_SEEDS):
             t0 = time.perf_counter()
             r = ctx.estimate(prob, cfg, SEED + 2 + rep)
             ts.append(time.perf_counter() - t0)
             ests.append(r["estimate"])
-        bs = closed_form(dict(GBM, kind="euro"))
-        out[name] = {"seconds": float(np.median(ts)), "estimate": float(np.mean(ests)),
-                     "rmse_bound": math.sqrt(r["variance"]), "path_steps": r["path_steps"],
-                     "errors_vs_closed_form": [float(e - bs) for e in ests]}
+            steps.append(r["path_steps"])
+        e = np.asarray(ests)
+        rmse = float(np.sqrt(np.mean((e - ref) ** 2)))
+        ci = [rmse * math.sqrt(TTE_SEEDS / CHI2_HI), rmse * math.sqrt(TTE_SEEDS / CHI2_LO)]
+        out[name] = {"seconds": float(np.median(ts)), "p10_s": float(np.percentile(ts, 10)),
+                     "p90_s": float(np.percentile(ts, 90)), "mean_estimate": float(e.mean()),
+                     "rmse": rmse, "rmse_ci95": ci, "rmse_within_eps": ci[0] <= EPS,
+                     "rmse_vs_closed_form": float(np.sqrt(np.mean((e - bs) ** 2))),
+                     "path_steps_median": float(np.median(steps))}
     out["speedup"] = out["plain_fp32"]["seconds"] / out["nested"]["seconds"]
+    out["faster_at_equal_rmse"] = bool(out["nested"]["rmse_within_eps"] and out["plain_fp32"]["rmse_within_eps"]
+                                       and out["speedup"] > 1.0)
     out["cost_ns_per_step"] = {"plain_fp32": c_p, "approx": c_a, "corr": c_c}
     return out
 

@@ -278,8 +278,8 @@ typedef struct mlmc_tuning {
 mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out);
 /* Chooses the launch geometry for a work list (host wall time per launch sequence
  * with `reps` sequences enqueued back to back, as a pipelined caller or the server
- * runs them, after a warm-up run): one pass of coordinate descent
- * over block_table {256, 512, 1024}, block_exact {64, 128, 256}, tile_steps
+ * runs them, after a warm-up run; the least of three such rounds): two passes of
+ * coordinate descent, the incumbent timed afresh at the start of each, over block_table {256, 512, 1024}, block_exact {64, 128, 256}, tile_steps
  * {2^14..2^18}, blocks_per_cu {2, 4, 8, 16}, min_tiles {512..4096} and zb_max_paths
  * {0, 2^13, 2^15, 2^17} and overlap_min_steps {0, 2^24, 2^26, 2^28, never},
  * starting from the context's current geometry and keeping

@@ -44,6 +44,21 @@ def _compile(hipcc, src):
     return obj, err
 
 
+PROBE_SRC = os.path.join(CSRC, "probe", "issue_rates.hip")
+PROBE = os.path.join(PKG, "issue_rates")
+
+
+def build_probe(hipcc):
+    """The VALU issue-rate probe (an executable beside the library)."""
+    tmp = PROBE + ".tmp"
+    cmd = [hipcc, "-x", "hip", *FLAGS, "-o", tmp, PROBE_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose=False):
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
@@ -60,6 +75,7 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe(hipcc)
     return LIB
 
 
