@@ -520,7 +520,9 @@ mlmc_status mlmc_validate(const mlmc_problem* prob, int32_t level, uint64_t n_pa
  * arithmetic and per-path records as mlmc_level_sums (sums are added in path
  * order rather than the kernels' tree order).  A checker of the kernel
  * arithmetic on machines without a GPU; no other entry point calls it.
- * out: as mlmc_level_sums; records: host array of n_paths records or NULL.
+ * out: as mlmc_level_sums; records: host array of n_paths records or NULL (then
+ * the kernels' sums-only code runs where they have one, as without a debug buffer:
+ * the level-0 loop of the exact-normal estimators).
  * Errors: MLMC_E_INVALID (validation, n_paths > 65536), MLMC_E_OVERFLOW. */
 mlmc_status mlmc_check_paths_host(const mlmc_problem* prob, int32_t level, uint64_t n_paths,
                                   uint64_t path_offset, const mlmc_precision* prec,

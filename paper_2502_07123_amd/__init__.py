@@ -282,14 +282,17 @@ def stream_words(seed, option, level, estimator, word_index, count):
     return out
 
 
-def check_paths_host(problem, level, n_paths, path_offset, prec, estimator, seed, option=0):
-    """The kernels' per-path code run on the host (a checker; n_paths <= 65536)."""
+def check_paths_host(problem, level, n_paths, path_offset, prec, estimator, seed, option=0,
+                     records=True):
+    """The kernels' per-path code run on the host (a checker; n_paths <= 65536).
+    Returns (sums per payoff, per-path records or None without records: the kernels'
+    sums-only code, e.g. the level-0 loop of the exact-normal estimators)."""
     names = _payoff_names(problem)
     out = (Sums * len(names))()
-    rec = np.zeros(int(n_paths), dtype=RECORD_DTYPE)
+    rec = np.zeros(int(n_paths), dtype=RECORD_DTYPE) if records else None
     check(lib().mlmc_check_paths_host(C.byref(problem), level, int(n_paths), int(path_offset),
                                       C.byref(prec), estimator, int(seed), option, out,
-                                      rec.ctypes.data_as(C.c_void_p)))
+                                      rec.ctypes.data_as(C.c_void_p) if records else None))
     return {n: out[i].as_dict() for i, n in enumerate(names)}, rec
 
 

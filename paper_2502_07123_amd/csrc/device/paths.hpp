@@ -727,6 +727,86 @@ struct PathBody {
         if (FIXED) acc.sat += c * ax.nsat;
     }
 
+    // ---- level 0 of the exact-normal estimators (plain; correction with a float
+    // table side), without a debug buffer.  A level-0 path is one step, so the loop is
+    // written for it (no step counting or coarse bookkeeping), and the correction
+    // estimator's approximate-side sample Ya -- a function of the path's table index
+    // alone -- comes from a per-index table built once per level (ya_sample), as the
+    // approximate estimator's level 0 does.  Each path's operations and the order in
+    // which they join the accumulator are those of run_group and finish, so the sums
+    // are the same bit for bit.
+    static constexpr bool EX0 = HAS_EXACT && !FIXED && F == 1;
+
+    // Ya(k) of each payoff slot (the FP64 view that sample() forms), written to
+    // yat[slot * entries + k]
+    __host__ __device__ __forceinline__ static void ya_sample(const LevelDev& L, const void* tab,
+                                                              uint32_t k, double* yat) {
+        FSide<ExactT> ex;
+        ex.init();
+        FSide<AT> ap;
+        XSide ax;
+        level0_path(L, tab, k, ap, ax);
+#pragma unroll
+        for (int slot = 0; slot < NP; ++slot) {
+            const int p = NP == 1 ? L.payoff_single : slot;
+            double y = 0.0;
+            if (NP == 1 || ((L.payoff_mask >> p) & 1u)) {
+                double Ye, Ya, Y;
+                int64_t Yint;
+                sample(L, p, ex, ap, ax, ExactT(L.k), ExactT(L.b), Ye, Ya, Yint, Y);
+                y = Ya;
+            }
+            yat[slot * L.table_entries + k] = y;
+        }
+    }
+
+    // The four level-0 paths 4g .. 4g + 3 of group g (one Philox block, one word per
+    // path); yat: the level's Ya table (correction estimator only).
+    __host__ __device__ __forceinline__ static void exact0_group(const LevelDev& L, const WorkDev& W,
+                                                                 uint64_t g, const void* tab,
+                                                                 const double* yat, Acc<NP>& acc) {
+        u32x4 r = philox4x32_10(
+            u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+        const uint64_t path0 = g * 4u;
+        const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
+        const ExactT eb = PLAIN32 ? ExactT(L.fb) : ExactT(L.b);
+        const int sh = 32 - L.q;
+        // a rolled loop keeps a single copy of the exact inverse normal (the words
+        // rotate through r.x); interleaving the four paths' normals measured no faster
+        // and costs registers
+#pragma unroll 1
+        for (int wi = 0; wi < 4; ++wi) {
+            const uint32_t J = r.x;
+            r.x = r.y;
+            r.y = r.z;
+            r.z = r.w;
+            FSide<ExactT> ex;
+            ex.init();
+            if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J), L, false, false, TRACK);
+            else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J)), L, false, false, TRACK);
+            const uint64_t pidx = path0 + static_cast<uint32_t>(wi);
+            if (pidx < W.path_begin || pidx >= W.path_end) continue;
+            const uint32_t k = HAS_TABLE ? (J >> sh) : 0u;
+#pragma unroll
+            for (int slot = 0; slot < NP; ++slot) {
+                const int p = NP == 1 ? L.payoff_single : slot;
+                if (NP != 1 && !((L.payoff_mask >> p) & 1u)) continue;
+                const ExactT pf = ex.payoff(p, true, 0, ek, eb);
+                const double Ye = static_cast<double>(pf - ExactT(0));
+                double Y = Ye;
+                if (EST == MLMC_EST_CORR) Y = Ye - yat[slot * L.table_entries + k];
+                if (!__builtin_isfinite(Y)) { acc.nonfinite += 1; Y = 0.0; }
+                acc.s1[slot] += Y;
+                acc.s2[slot] = fma(Y, Y, acc.s2[slot]);
+                if (EST == MLMC_EST_CORR) {
+                    acc.e1[slot] += Ye;
+                    acc.e2[slot] = fma(Ye, Ye, acc.e2[slot]);
+                }
+            }
+            acc.n += 1;
+        }
+    }
+
     __host__ __device__ __forceinline__ static void finish(const LevelDev& L, const WorkDev& W,
                                                            uint64_t pidx, const FSide<ExactT>& ex,
                                                            const FSide<AT>& ap, XSide& ax,

@@ -33,6 +33,13 @@ struct HostGroups {
             for (uint64_t g = g0; g < g1; ++g) B::hist_group(*L, *W, g, tab, count);
             for (uint32_t k = 0; k < L->table_entries; ++k)
                 if (hist[k]) B::hist_accumulate(*L, tab, k, hist[k], acc);
+        } else if (B::EX0 && L->level == 0 && !W->debug &&
+                   uint32_t(Tag::np) * L->table_entries <= YTAB_MAX_ENTRIES) {
+            // level 0 of the exact-normal estimators (no records), as the kernel runs it
+            std::vector<double> yat(size_t(Tag::np) * L->table_entries, 0.0);
+            if (B::HAS_TABLE)
+                for (uint32_t k = 0; k < L->table_entries; ++k) B::ya_sample(*L, tab, k, yat.data());
+            for (uint64_t g = g0; g < g1; ++g) B::exact0_group(*L, *W, g, tab, yat.data(), acc);
         } else if (B::HAS_EXACT && buffered) {
             // the buffered exact path: words and normals ahead, step-major, as k_normals
             using ZT = typename B::ExactT;

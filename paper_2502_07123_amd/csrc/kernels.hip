@@ -161,6 +161,13 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
                     if (!Body::ysample(L, s_tab, k, yt)) s_ybad = 1u;
                 __syncthreads();
                 ytab = s_ybad == 0u;
+            } else if (Body::EX0 && L.level == 0 && uint32_t(NP) * L.table_entries <= YTAB_MAX_ENTRIES) {
+                // the correction estimator's per-index approximate-side samples
+                double* yt = reinterpret_cast<double*>(s_tab + L.table_bytes);
+                for (uint32_t k = threadIdx.x; k < L.table_entries; k += blockDim.x)
+                    Body::ya_sample(L, s_tab, k, yt);
+                __syncthreads();
+                ytab = true;
             }
         }
         Acc<NP> acc;
@@ -184,6 +191,11 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
                 const uint32_t c = hist[k];
                 if (c) Body::hist_accumulate(L, s_tab, k, c, acc);
             }
+        } else if (Body::EX0 && L.level == 0 && !W.debug && (!Body::HAS_TABLE || ytab)) {
+            // level 0 of the exact-normal estimators: a group is one Philox block
+            const double* yt = reinterpret_cast<const double*>(s_tab + L.table_bytes);
+            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+                Body::exact0_group(L, W, g, s_tab, yt, acc);
         } else if (Body::HAS_EXACT && W.zbuf) {
             // normals computed ahead: a group is one path
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)

@@ -344,13 +344,16 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
                             (g.v.np == NPAY ? 4u : 0u);
             reds[wi].work = wi;
             // table, plus the level-0 index histogram of the approximate estimator or
-            // (FP32, small enough) its per-index sample table
+            // (FP32, small enough) its per-index sample table, or the correction
+            // estimator's per-index approximate-side samples (float table side)
             const LevelDev& Lw = levels[wdev[wi].lvl];
             uint32_t extra = 0;
+            const uint32_t ys = static_cast<uint32_t>(g.v.np) * Lw.table_entries;
             if (g.v.est == MLMC_EST_APPROX) {
                 extra = 4u * Lw.table_entries;
-                const uint32_t ys = static_cast<uint32_t>(g.v.np) * Lw.table_entries;
                 if (g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) extra = std::max(extra, 8u * ys);
+            } else if (g.v.est == MLMC_EST_CORR && g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) {
+                extra = 8u * ys;                  // the level-0 approximate-side samples
             }
             g.lds = std::max<uint32_t>(g.lds, Lw.table_bytes + extra);
         }

@@ -88,6 +88,25 @@ def test_sums_without_debug_equal_debug_run(ctx):
         assert a == b, (est, level)
 
 
+@pytest.mark.parametrize("est,arith,method,q", [(M.EST_CORR, "fp32", 1, 8), (M.EST_CORR, "fp16", 1, 8),
+                                                (M.EST_CORR, "fp32", 2, 8), (M.EST_CORR, "fp32", 1, 12),
+                                                (M.EST_PLAIN, "fp32", 1, 8), (M.EST_PLAIN, "fp64", 1, 8)])
+def test_level0_exact_loop_equals_debug_run(ctx, est, arith, method, q):
+    """Level 0 of the exact-normal estimators without a debug buffer runs its own loop
+    (the correction estimator's approximate side from per-index samples in LDS): the
+    same sums as the per-path code of a debug run, bit for bit, over several tiles and
+    ragged ends; one payoff (q = 12: the largest per-index table) or all five."""
+    for pays in (("euro",), PAYS):
+        if q == 12 and len(pays) > 1:
+            continue
+        prob = M.make_problem("milstein", pays, **GBM)
+        prec = M.make_precision(arith, q, method=method)
+        n = 1_000_003
+        a = ctx.level_sums(prob, 0, n, 5, prec, est, SEED)
+        b, _ = ctx.level_sums(prob, 0, n, 5, prec, est, SEED, debug=True)
+        assert a == b, (est, arith, method, q, pays)
+
+
 def test_repeatable_and_offset_split(ctx):
     """Bit-identical repeated runs; exact integer sums split over two path ranges add up."""
     prob = M.make_problem("euler", ("euro", "asian"), **GBM)

@@ -1,13 +1,15 @@
 """The kernels' per-path code compiled for the host (mlmc_check_paths_host) against
 the oracle, with the same bars as the GPU parity tests (tests/parity.py), without a
 GPU.  This pins the kernel arithmetic; the GPU tests add launch, tiling, reductions."""
+import math
+
 import numpy as np
 import pytest
 
 import paper_2502_07123_amd as M
 from oracle.paths import Precision, Problem, simulate
-from parity import (CASES, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q, check_records,
-                    oracle_run)
+from parity import (CASES, EST_CORR, EST_PLAIN, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q,
+                    check_records, oracle_run)
 
 
 @pytest.mark.parametrize("level", [0, 1, 3, 6])
@@ -52,3 +54,46 @@ def test_host_methods_2_3_match_oracle(mcase, level):
     sums, rec = M.check_paths_host(prob, level, n, off, prec, est, SEED)
     o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS, method=method, q=q)
     check_records(case, level, n, off, PAYS, sums, rec, o, q=q)
+
+
+EXACT0_CASES = [c for c in CASES if c[1] == EST_PLAIN or (c[1] == EST_CORR and c[2] != "fixed")]
+
+
+@pytest.mark.parametrize("case", EXACT0_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_level0_exact_loop_equals_per_path_code(case):
+    """Level 0 of the exact-normal estimators without records runs the kernels'
+    level-0 loop (per-index approximate-side samples for the correction estimator):
+    its sums equal those of the per-path code bit for bit (same operations, same
+    order of accumulation), and with an FP64 exact side they hold the oracle's
+    samples (plain FP32 per-path values are pinned by the record tests above)."""
+    scheme, est, arith, packed = case
+    n, off = 1001, 17                       # a ragged group at each end
+    prob = M.make_problem(scheme, PAYS, **GBM)
+    prec = M.make_precision(arith, case_q(case), packed, WIDE_FMT)
+    fast, none = M.check_paths_host(prob, 0, n, off, prec, est, SEED, records=False)
+    slow, rec = M.check_paths_host(prob, 0, n, off, prec, est, SEED)
+    assert none is None and rec is not None
+    o = oracle_run(case, 0, np.arange(off, off + n, dtype=np.uint64), PAYS)
+    for name in PAYS:
+        a, b = fast[name], slow[name]
+        for f in ("n", "sum1", "sum2", "esum1", "esum2", "nonfinite"):
+            assert a[f] == b[f], (name, f, a[f], b[f])
+        assert a["n"] == n
+        if arith == "fp32" and est == EST_PLAIN:
+            continue
+        Y = o[name]["Y"]
+        assert abs(a["sum1"] - math.fsum(Y)) <= 1e-9 * (np.sum(np.abs(Y)) + 1e-300)
+
+
+@pytest.mark.parametrize("q", [8, 12])
+def test_level0_exact_loop_method2_correction(q):
+    """Method 2's correction estimator (the exact side inverts the permuted word):
+    the level-0 loop's sums equal the per-path code's."""
+    case = ("euler", EST_CORR, "fp32", False)
+    prob = M.make_problem("euler", PAYS, **GBM)
+    prec = M.make_precision("fp32", q, False, WIDE_FMT, method=2)
+    fast, _ = M.check_paths_host(prob, 0, 777, 5, prec, EST_CORR, SEED, records=False)
+    slow, _ = M.check_paths_host(prob, 0, 777, 5, prec, EST_CORR, SEED)
+    for name in PAYS:
+        for f in ("n", "sum1", "sum2", "esum1", "esum2", "nonfinite"):
+            assert fast[name][f] == slow[name][f], (name, f)
