@@ -342,6 +342,7 @@ def calibrate(M, ctx, prob, prec_a, prec_c, level=4, n=1 << 22):
 
 
 TTE_SEEDS = 32
+TTE_PILOT = 10_000         # pilot paths per (level, estimator)
 # 2.5% and 97.5% quantiles of chi-square with 32 degrees of freedom: the 95% interval
 # of the true RMSE is rmse * sqrt(32 / q) for q in (CHI2_HI, CHI2_LO)
 CHI2_LO, CHI2_HI = 18.291, 49.480
@@ -379,7 +380,7 @@ def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale):
     out = {"reference_level_L": ref, "reference_se": ref_se, "closed_form": bs, "seeds": TTE_SEEDS}
     for name, nested in (("nested", True), ("plain_fp32", False)):
         cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", theta=1.0, L_min=8, L_max=8,
-                                n_pilot=20_000, costs=(c_p, c_a, c_c), plain_arith="fp32",
+                                n_pilot=TTE_PILOT, costs=(c_p, c_a, c_c), plain_arith="fp32",
                                 prec=prec_a)
         ctx.estimate(prob, cfg, SEED + 1)                  # warm (tables, caches)
         ts, ests, steps = [], [], []
