@@ -727,6 +727,87 @@ struct PathBody {
         if (FIXED) acc.sat += c * ax.nsat;
     }
 
+    // ---- the approximate estimator with a float table side above level 0: whole
+    // groups without a debug buffer.  Where a path starts and ends within the group is
+    // fixed by the level, so this loop places the initialisations and the final
+    // samples by construction instead of testing each step as the general code does
+    // (there the per-step tests become selects on every state variable).  The steps
+    // (table_step), samples (finish) and their order are the general code's, so the
+    // sums are the same bit for bit.  Power-of-two blocks of 4F positions only.
+    static constexpr bool FASTG = EST == MLMC_EST_APPROX && !FIXED && (WPB & (WPB - 1)) == 0;
+
+    // the 4F table indices of Philox block b, position by position
+    __host__ __device__ __forceinline__ static void block_indices(const WorkDev& W, uint64_t b, int q,
+                                                                  uint32_t (&k)[WPB]) {
+        const u32x4 r = philox4x32_10(
+            u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), W.c2, W.c3}, W.k0, W.k1);
+        const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int j = 0; j < WPB; ++j) k[j] = index_field(wd[j / F], j % F, q);
+    }
+
+    // levels with 2^LEV < 4F steps: block g holds 4F / 2^LEV whole paths
+    template <int LEV>
+    __host__ __device__ __forceinline__ static void short_paths(const LevelDev& L, const WorkDev& W,
+                                                                uint64_t g, const void* tab, Acc<NP>& acc) {
+        constexpr int N = 1 << LEV;
+        uint32_t k[WPB];
+        block_indices(W, g, L.q, k);
+        FSide<ExactT> ex;
+        FSide<AT> ap;
+        XSide ax;
+#pragma unroll
+        for (int j = 0; j < WPB; ++j) {
+            if ((j & (N - 1)) == 0) ap.init();
+            const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k[j]];
+            table_step<MIL, AT>(ap, e.z, e.s, L, true, (j & 1) != 0, TRACK);
+            if ((j & (N - 1)) == N - 1) finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
+        }
+    }
+
+    // levels with 2^level >= 4F steps: group g is path g, over 2^level / 4F blocks
+    __host__ __device__ __forceinline__ static void long_path(const LevelDev& L, const WorkDev& W,
+                                                              uint64_t g, const void* tab, Acc<NP>& acc) {
+        const uint32_t nblk = (1u << L.level) / WPB;
+        uint64_t b = g * nblk;
+        FSide<ExactT> ex;
+        FSide<AT> ap;
+        XSide ax;
+        ap.init();
+        for (uint32_t ib = 0; ib < nblk; ++ib, ++b) {
+            uint32_t k[WPB];
+            block_indices(W, b, L.q, k);
+#pragma unroll
+            for (int j = 0; j < WPB; ++j) {
+                const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k[j]];
+                table_step<MIL, AT>(ap, e.z, e.s, L, true, (j & 1) != 0, TRACK);
+            }
+        }
+        finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
+    }
+
+    // group g of a level >= 1 work: this loop when the group is whole and there is no
+    // debug buffer, else the general code
+    __host__ __device__ __forceinline__ static void run_group_fast(const LevelDev& L, const WorkDev& W,
+                                                                   uint64_t g, const void* tab,
+                                                                   Acc<NP>& acc) {
+        const int lev = L.level;
+        const uint64_t paths = lev < WPB_TZ ? uint64_t(WPB) >> lev : 1u;
+        const uint64_t path0 = g * paths;
+        if (lev == 0 || W.debug || path0 < W.path_begin || path0 + paths > W.path_end) {
+            run_group(L, W, g, tab, acc);
+            return;
+        }
+        switch (lev) {
+            case 1: if constexpr (WPB_TZ > 1) { short_paths<1>(L, W, g, tab, acc); return; } break;
+            case 2: if constexpr (WPB_TZ > 2) { short_paths<2>(L, W, g, tab, acc); return; } break;
+            case 3: if constexpr (WPB_TZ > 3) { short_paths<3>(L, W, g, tab, acc); return; } break;
+            case 4: if constexpr (WPB_TZ > 4) { short_paths<4>(L, W, g, tab, acc); return; } break;
+            default: break;
+        }
+        long_path(L, W, g, tab, acc);
+    }
+
     // ---- level 0 of the exact-normal estimators (plain; correction with a float
     // table side), without a debug buffer.  A level-0 path is one step, so the loop is
     // written for it (no step counting or coarse bookkeeping), and the correction

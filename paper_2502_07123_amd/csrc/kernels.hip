@@ -122,14 +122,17 @@ __device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r)
     block_store_counts<NP, CORR, INTS>(a, a.n, a.sat, a.nonfinite, out, r);
 }
 
-// Exact-normal kernels carry the FP64 inverse normal's constants and fixed-point
-// kernels the wide integer sums: they get a 256-thread bound (more registers per
-// lane, no spills); FP32 table-only kernels 1024.
-template <int EST, int ARITH>
-constexpr int max_threads() { return EST == MLMC_EST_APPROX && ARITH != MLMC_ARITH_FIXED ? 1024 : 256; }
+// Exact-normal kernels carry the FP64 inverse normal's constants, fixed-point kernels
+// the wide integer sums and all-payoff kernels five payoffs' sums and path
+// functionals: they get a 256-thread bound (more registers per lane, no spills);
+// single-payoff float table-only kernels 1024.
+template <int EST, int ARITH, int NP>
+constexpr int max_threads() {
+    return EST == MLMC_EST_APPROX && ARITH != MLMC_ARITH_FIXED && NP == 1 ? 1024 : 256;
+}
 
 template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64, max_threads<EST, ARITH>())))
+__global__ void __attribute__((amdgpu_flat_work_group_size(64, max_threads<EST, ARITH, NP>())))
 k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles,
         const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
         const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
@@ -200,6 +203,10 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
             // normals computed ahead: a group is one path
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::run_path_buffered(L, W, g, s_tab, acc);
+        } else if (Body::FASTG && L.level >= 1 && !W.debug) {
+            // whole groups of the approximate estimator: path boundaries by construction
+            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+                Body::run_group_fast(L, W, g, s_tab, acc);
         } else {
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::run_group(L, W, g, s_tab, acc);
@@ -328,7 +335,7 @@ struct InfoOf {
         using B = PathBody<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields>;
         out = VariantInfo{reinterpret_cast<void*>(
                               &k_paths<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields>),
-                          B::WPB, B::TAB_BYTES, max_threads<Tag::est, Tag::arith>()};
+                          B::WPB, B::TAB_BYTES, max_threads<Tag::est, Tag::arith, Tag::np>()};
     }
 };
 }  // namespace

@@ -119,3 +119,20 @@ def test_repeatable_and_offset_split(ctx):
     for p in ("euro", "asian"):
         assert c1[p]["isum1"] + c2[p]["isum1"] == a[p]["isum1"]
         assert c1[p]["isum2"] + c2[p]["isum2"] == a[p]["isum2"]
+
+
+@pytest.mark.parametrize("arith,q,packed", [("fp32", 8, True), ("fp32", 4, True), ("fp32", 8, False),
+                                            ("fp16", 8, True)])
+def test_approx_group_loop_equals_debug_run(ctx, arith, q, packed):
+    """Levels >= 1 of the approximate estimator without a debug buffer run whole groups
+    through a loop with path boundaries placed by construction: the same sums as the
+    per-path code of a debug run, bit for bit, over many tiles and ragged ends; one
+    payoff and all five (path functionals)."""
+    for pays in (("euro",), PAYS):
+        prob = M.make_problem("milstein", pays, **GBM)
+        prec = M.make_precision(arith, q, packed)
+        for level in (1, 2, 3, 4, 6):
+            n = (1 << 21) // (1 << level) + 7
+            a = ctx.level_sums(prob, level, n, 9, prec, M.EST_APPROX, SEED)
+            b, _ = ctx.level_sums(prob, level, n, 9, prec, M.EST_APPROX, SEED, debug=True)
+            assert a == b, (arith, q, packed, pays, level)

@@ -8,7 +8,7 @@ import pytest
 
 import paper_2502_07123_amd as M
 from oracle.paths import Precision, Problem, simulate
-from parity import (CASES, EST_CORR, EST_PLAIN, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q,
+from parity import (CASES, EST_APPROX, EST_CORR, EST_PLAIN, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q,
                     check_records, oracle_run)
 
 
@@ -96,4 +96,23 @@ def test_level0_exact_loop_method2_correction(q):
     slow, _ = M.check_paths_host(prob, 0, 777, 5, prec, EST_CORR, SEED)
     for name in PAYS:
         for f in ("n", "sum1", "sum2", "esum1", "esum2", "nonfinite"):
+            assert fast[name][f] == slow[name][f], (name, f)
+
+
+@pytest.mark.parametrize("level", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("arith,q,packed", [("fp32", 8, True), ("fp32", 4, True), ("fp32", 8, False),
+                                            ("fp16", 8, True), ("fp32", 6, True)])
+@pytest.mark.parametrize("pays", [("euro",), PAYS], ids=["one", "all"])
+def test_approx_group_loop_equals_per_path_code(level, arith, q, packed, pays):
+    """Above level 0 the approximate estimator's whole groups (no records) run a loop
+    that places path starts and ends by construction: the same sums as the per-path
+    code, bit for bit, with ragged groups at both ends (q = 6: five fields per word,
+    the general code throughout)."""
+    n, off = 901, 13
+    prob = M.make_problem("milstein", pays, **GBM)
+    prec = M.make_precision(arith, q, packed)
+    fast, _ = M.check_paths_host(prob, level, n, off, prec, EST_APPROX, SEED, records=False)
+    slow, _ = M.check_paths_host(prob, level, n, off, prec, EST_APPROX, SEED)
+    for name in pays:
+        for f in ("n", "sum1", "sum2", "nonfinite"):
             assert fast[name][f] == slow[name][f], (name, f)
