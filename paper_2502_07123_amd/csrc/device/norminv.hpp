@@ -58,25 +58,57 @@ static __constant__ double g_ninv64_pt[ninv64::DEG_T + 1] = NINV64_PT_INIT;
 #define NINV64_PT ninv64::PT
 #endif
 
-__host__ __device__ __forceinline__ double norminv_f64(uint32_t J) {
-    using namespace ninv64;
+// The inverse normal in three parts: the argument (y = 2U - 1, w), the central
+// polynomial y P(w - C_MID) and the tail Q(sqrt(w) - T_MID) with y's sign; the value
+// is the central one for w < W1, else the tail one.
+template <typename T>
+struct NinvArg {
+    T y, w;
+};
+
+__host__ __device__ __forceinline__ NinvArg<double> ninv64_arg(uint32_t J) {
     const int32_t sj = static_cast<int32_t>(J ^ 0x80000000u);
     const double y = (static_cast<double>(sj) + 0.5) * 0x1p-31;       // 2U - 1, exact
     const uint32_t v = (J < 0x80000000u) ? J : ~J;
     const double us = (static_cast<double>(v) + 0.5) * 0x1p-32;       // min(U, 1-U), exact
-    const double w = -log_unit((us * (1.0 - us)) * 4.0);
-    if (w < W1) {
-        const double t = w - C_MID;
-        double p = NINV64_PC[DEG_C];
+    return NinvArg<double>{y, -log_unit((us * (1.0 - us)) * 4.0)};
+}
+
+__host__ __device__ __forceinline__ double ninv64_central(const NinvArg<double>& a) {
+    using namespace ninv64;
+    const double t = a.w - C_MID;
+    double p = NINV64_PC[DEG_C];
 #pragma unroll
-        for (int k = DEG_C - 1; k >= 0; --k) p = fma(p, t, NINV64_PC[k]);
-        return y * p;
-    }
-    const double t = sqrt(w) - T_MID;
+    for (int k = DEG_C - 1; k >= 0; --k) p = fma(p, t, NINV64_PC[k]);
+    return a.y * p;
+}
+
+__host__ __device__ __forceinline__ double ninv64_tail(const NinvArg<double>& a) {
+    using namespace ninv64;
+    const double t = sqrt(a.w) - T_MID;
     double p = NINV64_PT[DEG_T];
 #pragma unroll
     for (int k = DEG_T - 1; k >= 0; --k) p = fma(p, t, NINV64_PT[k]);
-    return copysign(p, y);
+    return copysign(p, a.y);
+}
+
+__host__ __device__ __forceinline__ double norminv_f64(uint32_t J) {
+    const NinvArg<double> a = ninv64_arg(J);
+    return a.w < ninv64::W1 ? ninv64_central(a) : ninv64_tail(a);
+}
+
+// Four inverse normals with the same values as norminv_f64: the arguments and the
+// central values of all four first, branch-free, so that their dependency chains
+// interleave; the rare tail inputs (w >= W1, about 1e-3 of them) are redone after.
+__host__ __device__ __forceinline__ void norminv_f64_x4(const uint32_t (&J)[4], double (&Z)[4]) {
+    NinvArg<double> a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = ninv64_arg(J[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Z[i] = ninv64_central(a[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (!(a[i].w < ninv64::W1)) Z[i] = ninv64_tail(a[i]);
 }
 
 __host__ __device__ __forceinline__ float fast_logf(float x) {
@@ -87,25 +119,47 @@ __host__ __device__ __forceinline__ float fast_logf(float x) {
 #endif
 }
 
-__host__ __device__ __forceinline__ float norminv_f32(uint32_t J) {
-    using namespace ninv32;
+__host__ __device__ __forceinline__ NinvArg<float> ninv32_arg(uint32_t J) {
     const int32_t sj = static_cast<int32_t>(J ^ 0x80000000u);
     const float y = (static_cast<float>(sj) + 0.5f) * 0x1p-31f;        // 2U - 1
     const uint32_t v = (J < 0x80000000u) ? J : ~J;
     const float us = (static_cast<float>(v) + 0.5f) * 0x1p-32f;        // min(U, 1-U)
-    const float w = -fast_logf((us * (1.0f - us)) * 4.0f);
-    if (w < W1) {
-        const float t = w - C_MID;
-        float p = PC[DEG_C];
+    return NinvArg<float>{y, -fast_logf((us * (1.0f - us)) * 4.0f)};
+}
+
+__host__ __device__ __forceinline__ float ninv32_central(const NinvArg<float>& a) {
+    using namespace ninv32;
+    const float t = a.w - C_MID;
+    float p = PC[DEG_C];
 #pragma unroll
-        for (int k = DEG_C - 1; k >= 0; --k) p = fmaf(p, t, PC[k]);
-        return y * p;
-    }
-    const float t = sqrtf(w) - T_MID;
+    for (int k = DEG_C - 1; k >= 0; --k) p = fmaf(p, t, PC[k]);
+    return a.y * p;
+}
+
+__host__ __device__ __forceinline__ float ninv32_tail(const NinvArg<float>& a) {
+    using namespace ninv32;
+    const float t = sqrtf(a.w) - T_MID;
     float p = PT[DEG_T];
 #pragma unroll
     for (int k = DEG_T - 1; k >= 0; --k) p = fmaf(p, t, PT[k]);
-    return copysignf(p, y);
+    return copysignf(p, a.y);
+}
+
+__host__ __device__ __forceinline__ float norminv_f32(uint32_t J) {
+    const NinvArg<float> a = ninv32_arg(J);
+    return a.w < ninv32::W1 ? ninv32_central(a) : ninv32_tail(a);
+}
+
+// four FP32 inverse normals, as norminv_f64_x4
+__host__ __device__ __forceinline__ void norminv_f32_x4(const uint32_t (&J)[4], float (&Z)[4]) {
+    NinvArg<float> a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = ninv32_arg(J[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Z[i] = ninv32_central(a[i]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (!(a[i].w < ninv32::W1)) Z[i] = ninv32_tail(a[i]);
 }
 
 }  // namespace mlmc

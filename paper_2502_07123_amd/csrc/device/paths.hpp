@@ -786,7 +786,72 @@ struct PathBody {
         finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
     }
 
-    // group g of a level >= 1 work: this loop when the group is whole and there is no
+    // The same loop for the exact-normal estimators (plain; correction with a float
+    // table side), one word per step (F = 1): steps come in (even, odd) pairs, and the
+    // pairs run in a rolled loop so that one copy of the inverse normal serves each
+    // parity.
+    static constexpr bool EXG = HAS_EXACT && !FIXED && F == 1;
+
+    // the (even, odd) step pair of words (J0, J1): exact side, then the table side
+    __host__ __device__ __forceinline__ static void exact_pair(const LevelDev& L, const void* tab, uint32_t J0,
+                                                               uint32_t J1, FSide<ExactT>& ex, FSide<AT>& ap) {
+        const int sh = 32 - L.q;
+        if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J0), L, true, false, TRACK);
+        else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J0)), L, true, false, TRACK);
+        if (HAS_TABLE) {
+            const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[J0 >> sh];
+            table_step<MIL, AT>(ap, e.z, e.s, L, true, false, TRACK);
+        }
+        if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J1), L, true, true, TRACK);
+        else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J1)), L, true, true, TRACK);
+        if (HAS_TABLE) {
+            const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[J1 >> sh];
+            table_step<MIL, AT>(ap, e.z, e.s, L, true, true, TRACK);
+        }
+    }
+
+    __host__ __device__ __forceinline__ static void exact_group_fast(const LevelDev& L, const WorkDev& W,
+                                                                     uint64_t g, const void* tab,
+                                                                     Acc<NP>& acc) {
+        FSide<ExactT> ex;
+        FSide<AT> ap;
+        XSide ax;
+        if (L.level == 1) {
+            // block g holds paths 2g and 2g + 1, two steps each
+            u32x4 r = philox4x32_10(
+                u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+#pragma unroll 1
+            for (int p = 0; p < 2; ++p) {
+                const uint32_t J0 = r.x, J1 = r.y;
+                r.x = r.z;
+                r.y = r.w;
+                ex.init();
+                if (HAS_TABLE) ap.init();
+                exact_pair(L, tab, J0, J1, ex, ap);
+                finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
+            }
+            return;
+        }
+        // level >= 2: path g over 2^level / 4 blocks, two pairs per block
+        const uint32_t nblk = (1u << L.level) / 4u;
+        uint64_t b = g * nblk;
+        ex.init();
+        if (HAS_TABLE) ap.init();
+        for (uint32_t ib = 0; ib < nblk; ++ib, ++b) {
+            u32x4 r = philox4x32_10(
+                u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), W.c2, W.c3}, W.k0, W.k1);
+#pragma unroll 1
+            for (int p = 0; p < 2; ++p) {
+                const uint32_t J0 = r.x, J1 = r.y;
+                r.x = r.z;
+                r.y = r.w;
+                exact_pair(L, tab, J0, J1, ex, ap);
+            }
+        }
+        finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
+    }
+
+    // group g of a level >= 1 work: these loops when the group is whole and there is no
     // debug buffer, else the general code
     __host__ __device__ __forceinline__ static void run_group_fast(const LevelDev& L, const WorkDev& W,
                                                                    uint64_t g, const void* tab,
@@ -798,14 +863,18 @@ struct PathBody {
             run_group(L, W, g, tab, acc);
             return;
         }
-        switch (lev) {
-            case 1: if constexpr (WPB_TZ > 1) { short_paths<1>(L, W, g, tab, acc); return; } break;
-            case 2: if constexpr (WPB_TZ > 2) { short_paths<2>(L, W, g, tab, acc); return; } break;
-            case 3: if constexpr (WPB_TZ > 3) { short_paths<3>(L, W, g, tab, acc); return; } break;
-            case 4: if constexpr (WPB_TZ > 4) { short_paths<4>(L, W, g, tab, acc); return; } break;
-            default: break;
+        if constexpr (EXG) {
+            exact_group_fast(L, W, g, tab, acc);
+        } else {
+            switch (lev) {
+                case 1: if constexpr (WPB_TZ > 1) { short_paths<1>(L, W, g, tab, acc); return; } break;
+                case 2: if constexpr (WPB_TZ > 2) { short_paths<2>(L, W, g, tab, acc); return; } break;
+                case 3: if constexpr (WPB_TZ > 3) { short_paths<3>(L, W, g, tab, acc); return; } break;
+                case 4: if constexpr (WPB_TZ > 4) { short_paths<4>(L, W, g, tab, acc); return; } break;
+                default: break;
+            }
+            long_path(L, W, g, tab, acc);
         }
-        long_path(L, W, g, tab, acc);
     }
 
     // ---- level 0 of the exact-normal estimators (plain; correction with a float
@@ -846,25 +915,30 @@ struct PathBody {
     __host__ __device__ __forceinline__ static void exact0_group(const LevelDev& L, const WorkDev& W,
                                                                  uint64_t g, const void* tab,
                                                                  const double* yat, Acc<NP>& acc) {
-        u32x4 r = philox4x32_10(
+        const u32x4 r = philox4x32_10(
             u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+        const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
         const uint64_t path0 = g * 4u;
         const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
         const ExactT eb = PLAIN32 ? ExactT(L.fb) : ExactT(L.b);
         const int sh = 32 - L.q;
-        // a rolled loop keeps a single copy of the exact inverse normal (the words
-        // rotate through r.x); interleaving the four paths' normals measured no faster
-        // and costs registers
-#pragma unroll 1
+        // the four inverse normals together (norminv_*_x4: interleaved chains, the
+        // rare tails after), the same values as one at a time
+        ExactT Z[4];
+        if constexpr (PLAIN32) {
+            norminv_f32_x4(wd, Z);
+        } else {
+            uint32_t Je[4];
+#pragma unroll
+            for (int wi = 0; wi < 4; ++wi) Je[wi] = coupled_word(L, tab, wd[wi]);
+            norminv_f64_x4(Je, Z);
+        }
+#pragma unroll
         for (int wi = 0; wi < 4; ++wi) {
-            const uint32_t J = r.x;
-            r.x = r.y;
-            r.y = r.z;
-            r.z = r.w;
+            const uint32_t J = wd[wi];
             FSide<ExactT> ex;
             ex.init();
-            if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J), L, false, false, TRACK);
-            else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J)), L, false, false, TRACK);
+            exact_step<MIL>(ex, Z[wi], L, false, false, TRACK);
             const uint64_t pidx = path0 + static_cast<uint32_t>(wi);
             if (pidx < W.path_begin || pidx >= W.path_end) continue;
             const uint32_t k = HAS_TABLE ? (J >> sh) : 0u;

@@ -63,7 +63,7 @@ struct HostGroups {
             W2.jbuf = reinterpret_cast<uint64_t>(Jb.data());
             W2.zbuf = reinterpret_cast<uint64_t>(Zb.data());
             for (uint64_t i = W->path_begin; i < W->path_end; ++i) B::run_path_buffered(*L, W2, i, tab, acc);
-        } else if (B::FASTG && L->level >= 1 && !W->debug) {
+        } else if ((B::FASTG || B::EXG) && L->level >= 1 && !W->debug) {
             for (uint64_t g = g0; g < g1; ++g) B::run_group_fast(*L, *W, g, tab, acc);
         } else {
             for (uint64_t g = g0; g < g1; ++g) B::run_group(*L, *W, g, tab, acc);

@@ -203,8 +203,8 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
             // normals computed ahead: a group is one path
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::run_path_buffered(L, W, g, s_tab, acc);
-        } else if (Body::FASTG && L.level >= 1 && !W.debug) {
-            // whole groups of the approximate estimator: path boundaries by construction
+        } else if ((Body::FASTG || Body::EXG) && L.level >= 1 && !W.debug) {
+            // whole groups above level 0: path boundaries by construction
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::run_group_fast(L, W, g, s_tab, acc);
         } else {
@@ -215,10 +215,14 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
     }
 }
 
-// Exact normals ahead of the path kernel for works with few, long paths: tiles
-// are ranges of Philox blocks b of the work's stream (positions 4b .. 4b + 3);
-// each thread computes one block's four words and their exact normals and stores
-// them step-major (index n P + path offset) so the path kernel reads coalesced.
+// Exact normals ahead of the path kernel for works with few, long paths (level >= 2,
+// so a Philox block is four steps of one path): tiles are ranges of x = m P + c over
+// the work's blocks in column order (c the path offset, m the block within the path,
+// block b = (path_begin + c) 2^level / 4 + m).  Each thread computes one block's four
+// words and their exact normals (norminv_*_x4: four chains that interleave) and
+// stores them step-major (index n P + c, n = 4 m + w): consecutive
+// threads take consecutive paths, so each store is a contiguous row segment and the
+// path kernel reads coalesced.
 template <bool F32>
 __global__ void __launch_bounds__(256)
 k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __restrict__ works,
@@ -236,20 +240,26 @@ k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __
         const uint64_t P = W.path_end - W.path_begin;
         MLMC_GLOBAL ZT* Zb = global_ptr<ZT>(W.zbuf);
         MLMC_GLOBAL uint32_t* Jb = global_ptr<uint32_t>(W.jbuf);
-        const uint64_t bend = td.group_begin + td.n_groups;
-        for (uint64_t b = td.group_begin + threadIdx.x; b < bend; b += blockDim.x) {
+        const uint64_t xend = td.group_begin + td.n_groups;
+        const uint64_t bpp = (uint64_t(1) << lev) / 4;              // blocks per path
+        for (uint64_t x = td.group_begin + threadIdx.x; x < xend; x += blockDim.x) {
+            const uint64_t m = x / P, c = x - m * P;
+            const uint64_t b = (W.path_begin + c) * bpp + m;
             const u32x4 r = philox4x32_10(
                 u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), W.c2, W.c3}, W.k0, W.k1);
             const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll 1
+            uint32_t Je[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                Je[w] = pi ? (uint32_t(pi[wd[w] >> sh]) << sh) | (wd[w] & ((1u << sh) - 1u)) : wd[w];
+            ZT Z[4];
+            if constexpr (F32) norminv_f32_x4(Je, Z);
+            else norminv_f64_x4(Je, Z);
+#pragma unroll
             for (int w = 0; w < 4; ++w) {
-                const uint64_t g = 4 * b + w;
-                const uint64_t i = g >> lev, n = g & ((uint64_t(1) << lev) - 1);
-                const uint64_t idx = n * P + (i - W.path_begin);
+                const uint64_t idx = (4 * m + w) * P + c;
                 Jb[idx] = wd[w];
-                const uint32_t Je = pi ? (uint32_t(pi[wd[w] >> sh]) << sh) | (wd[w] & ((1u << sh) - 1u)) : wd[w];
-                if (F32) Zb[idx] = static_cast<ZT>(norminv_f32(Je));
-                else Zb[idx] = static_cast<ZT>(norminv_f64(Je));
+                Zb[idx] = Z[w];
             }
         }
     }

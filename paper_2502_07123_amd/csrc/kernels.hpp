@@ -90,6 +90,9 @@ hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, si
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
                         SlotDev* slots);
 
+// Philox blocks per tile of the normals-ahead kernel (one per thread of its 256)
+constexpr uint64_t NORMALS_TILE_BLOCKS = 256;
+
 // exact normals ahead of the path kernel (FP32 for the plain-FP32 estimator, else FP64)
 hipError_t launch_normals(bool f32, uint32_t grid, hipStream_t st, const TileDev* tiles,
                           uint32_t n_tiles, const WorkDev* works, const LevelDev* levels,

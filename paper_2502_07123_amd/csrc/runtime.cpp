@@ -297,13 +297,17 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
                 zb_f32[wi] = f32 ? 1 : 0;
                 const uint64_t pos = w.n << w.level;
                 zb_bytes[wi] = align_up(pos * 4, 256) + align_up(pos * (f32 ? 4 : 8), 256);
-                const uint64_t b0 = (w.path_begin << w.level) / 4, b1 = ((w.path_begin + w.n) << w.level) / 4;
-                for (uint64_t b = b0; b < b1; b += 1024) {
+                // the work's Philox blocks in column order, x = (step / 4) P + path
+                // offset (the normals kernel's index), one per thread of a 256-thread
+                // normals block: enough workgroups to hide the inverse normal's
+                // dependent FP64 chains, and each store a contiguous row segment
+                const uint64_t x1 = pos / 4;
+                for (uint64_t x = 0; x < x1; x += NORMALS_TILE_BLOCKS) {
                     TileDev t;
                     t.work = wi;
                     t.slot = 0;
-                    t.group_begin = b;
-                    t.n_groups = static_cast<uint32_t>(std::min<uint64_t>(1024, b1 - b));
+                    t.group_begin = x;
+                    t.n_groups = static_cast<uint32_t>(std::min<uint64_t>(NORMALS_TILE_BLOCKS, x1 - x));
                     t.pad = 0;
                     ntiles[f32 ? 1 : 0].push_back(t);
                 }

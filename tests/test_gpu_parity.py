@@ -136,3 +136,20 @@ def test_approx_group_loop_equals_debug_run(ctx, arith, q, packed):
             a = ctx.level_sums(prob, level, n, 9, prec, M.EST_APPROX, SEED)
             b, _ = ctx.level_sums(prob, level, n, 9, prec, M.EST_APPROX, SEED, debug=True)
             assert a == b, (arith, q, packed, pays, level)
+
+
+@pytest.mark.parametrize("est,arith,method", [(M.EST_PLAIN, "fp64", 1), (M.EST_PLAIN, "fp32", 1),
+                                              (M.EST_CORR, "fp32", 1), (M.EST_CORR, "fp16", 1),
+                                              (M.EST_CORR, "fp32", 2)])
+def test_exact_group_loop_equals_debug_run(ctx, est, arith, method):
+    """Levels >= 1 of the exact-normal estimators without a debug buffer run whole
+    groups as (even, odd) step pairs with path boundaries by construction: the same
+    sums as the per-path code of a debug run, bit for bit (70,001 paths: more than the
+    normals-ahead limit, so every level runs the loop)."""
+    for pays in (("euro",), PAYS):
+        prob = M.make_problem("milstein", pays, **GBM)
+        prec = M.make_precision(arith, 8, method=method)
+        for level in (1, 2, 3, 5):
+            a = ctx.level_sums(prob, level, 70_001, 11, prec, est, SEED)
+            b, _ = ctx.level_sums(prob, level, 70_001, 11, prec, est, SEED, debug=True)
+            assert a == b, (est, arith, method, pays, level)

@@ -116,3 +116,35 @@ def test_approx_group_loop_equals_per_path_code(level, arith, q, packed, pays):
     for name in pays:
         for f in ("n", "sum1", "sum2", "nonfinite"):
             assert fast[name][f] == slow[name][f], (name, f)
+
+
+@pytest.mark.parametrize("level", [1, 2, 3, 5])
+@pytest.mark.parametrize("case", [("milstein", EST_PLAIN, "fp64"), ("euler", EST_PLAIN, "fp32"),
+                                  ("milstein", EST_CORR, "fp32"), ("euler", EST_CORR, "fp16"),
+                                  ("milstein", EST_CORR, "fixed")], ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("pays", [("euro",), PAYS], ids=["one", "all"])
+def test_exact_group_loop_equals_per_path_code(level, case, pays):
+    """Above level 0 the exact-normal estimators' whole groups (no records) run a loop
+    of (even, odd) step pairs with path boundaries by construction: the same sums as
+    the per-path code, bit for bit (fixed point: the general code throughout)."""
+    scheme, est, arith = case
+    n, off = 333, 5
+    prob = M.make_problem(scheme, pays, **GBM)
+    prec = M.make_precision(arith, 8, False, WIDE_FMT if arith == "fixed" else None)
+    fast, _ = M.check_paths_host(prob, level, n, off, prec, est, SEED, records=False)
+    slow, _ = M.check_paths_host(prob, level, n, off, prec, est, SEED)
+    for name in pays:
+        for f in ("n", "sum1", "sum2", "esum1", "esum2", "nonfinite", "isum1"):
+            assert fast[name][f] == slow[name][f], (name, f)
+
+
+def test_method2_correction_group_loop():
+    """Method 2's permuted coupled word on the exact side, above level 0."""
+    prob = M.make_problem("euler", PAYS, **GBM)
+    prec = M.make_precision("fp32", 8, False, WIDE_FMT, method=2)
+    for level in (1, 3):
+        fast, _ = M.check_paths_host(prob, level, 555, 3, prec, EST_CORR, SEED, records=False)
+        slow, _ = M.check_paths_host(prob, level, 555, 3, prec, EST_CORR, SEED)
+        for name in PAYS:
+            for f in ("n", "sum1", "sum2", "esum1", "esum2"):
+                assert fast[name][f] == slow[name][f], (name, f, level)
