@@ -786,6 +786,19 @@ struct PathBody {
         finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
     }
 
+    // Philox block b of W's stream for the exact-normal loops.  The keys are marked
+    // as rewritten here, so their 20 round keys are formed per call by scalar adds
+    // instead of being hoisted out of the loop, where beside the FP64 inverse
+    // normal's coefficients they outgrow the scalar registers and end up in
+    // vector-register lanes (a v_readlane and a wait state per round).
+    __host__ __device__ __forceinline__ static u32x4 philox_group_keys(const WorkDev& W, uint64_t b) {
+        uint32_t k0 = W.k0, k1 = W.k1;
+#if defined(__HIP_DEVICE_COMPILE__)
+        asm volatile("" : "+s"(k0), "+s"(k1));
+#endif
+        return philox4x32_10(u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), W.c2, W.c3}, k0, k1);
+    }
+
     // The same loop for the exact-normal estimators (plain; correction with a float
     // table side), one word per step (F = 1): steps come in (even, odd) pairs, and the
     // pairs run in a rolled loop so that one copy of the inverse normal serves each
@@ -818,8 +831,7 @@ struct PathBody {
         XSide ax;
         if (L.level == 1) {
             // block g holds paths 2g and 2g + 1, two steps each
-            u32x4 r = philox4x32_10(
-                u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+            u32x4 r = philox_group_keys(W, g);
 #pragma unroll 1
             for (int p = 0; p < 2; ++p) {
                 const uint32_t J0 = r.x, J1 = r.y;
@@ -838,8 +850,7 @@ struct PathBody {
         ex.init();
         if (HAS_TABLE) ap.init();
         for (uint32_t ib = 0; ib < nblk; ++ib, ++b) {
-            u32x4 r = philox4x32_10(
-                u32x4{static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32), W.c2, W.c3}, W.k0, W.k1);
+            u32x4 r = philox_group_keys(W, b);
 #pragma unroll 1
             for (int p = 0; p < 2; ++p) {
                 const uint32_t J0 = r.x, J1 = r.y;
@@ -915,8 +926,7 @@ struct PathBody {
     __host__ __device__ __forceinline__ static void exact0_group(const LevelDev& L, const WorkDev& W,
                                                                  uint64_t g, const void* tab,
                                                                  const double* yat, Acc<NP>& acc) {
-        const u32x4 r = philox4x32_10(
-            u32x4{static_cast<uint32_t>(g), static_cast<uint32_t>(g >> 32), W.c2, W.c3}, W.k0, W.k1);
+        const u32x4 r = philox_group_keys(W, g);
         const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
         const uint64_t path0 = g * 4u;
         const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
