@@ -11,7 +11,8 @@ sequence plus the host combination into the price estimate; consecutive steps ar
 pipelined (the host marshals and enqueues step k + 1 while step k runs).
 
 Printed: one JSON line (metric path-steps/s), with the VALU roofline of the
-dominant kernel (HIP-event timing inside the timed region), the CPU oracle timed on
+dominant kernel (the one with the most algorithmic work; HIP-event timing inside
+the timed region), the CPU oracle timed on
 a bounded sample, and the time to RMSE eps of the nested estimator against plain
 FP32 MLMC on the same GPU.
 """
@@ -263,16 +264,17 @@ def main():
     ms_step = dt * 1e3 / args.steps
     value = path_steps / (dt / args.steps)
 
-    # roofline of the dominant kernel (largest event time in the timed region)
-    dom = max(stats, key=lambda s: s["ms"])
+    # roofline of the dominant kernel: the one with the most algorithmic work per step
+    # (event times are no guide when the two streams' kernels run concurrently: an
+    # event pair also spans the time its kernel waits behind the other stream's)
+    def kernel_ops(k):
+        # algorithmic ops of the kernel's works, level by level (its level mix)
+        N = Na if k["estimator"] == M.EST_APPROX else Nc
+        return sum(int(N[l]) * (1 << l) * alg_ops_per_step(k["estimator"], k["fields"], k["scheme"], l)
+                   for l in range(LEVELS))
+    dom = max(stats, key=kernel_ops)
     per_step_steps = dom["path_steps"] / args.steps
-    # algorithmic ops of that kernel's works, level by level (its level mix)
-    if dom["estimator"] == M.EST_APPROX:
-        mix = [(l, int(Na[l])) for l in range(LEVELS)]
-    else:
-        mix = [(l, int(Nc[l])) for l in range(LEVELS)]
-    ops = sum(n * (1 << l) * alg_ops_per_step(dom["estimator"], dom["fields"], dom["scheme"], l)
-              for l, n in mix)
+    ops = kernel_ops(dom)
     # the kernel's time per step (its launches of one step together cover the mix)
     avg_s = dom["ms"] / args.steps * 1e-3
     achieved = ops / avg_s
