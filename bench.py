@@ -48,7 +48,9 @@ def alg_ops_per_step(est, fields, scheme, level):
     """Algorithmic lane-ops per fine path-step of one coupled sample.
     Table side (FP32, Algorithm 1 per operation): fine step mul + add (2); coarse step
     per fine pair: zsum, mul1, sum1, mul2, X-add (5), Milstein + zsq, zm1, mul3, sum2 (9);
-    index: shift (+ mask when packed).  Per path: payoff and level difference (~8)."""
+    index: shift (+ mask when packed).  Per path: payoff and level difference (~8).
+    The exact-normal estimators count the generator and the payoff only (a lower
+    bound: their inverse normals and FP64 steps are not counted)."""
     mil = scheme == 1
     wpb = 4 * fields
     ops = philox_ops() / wpb
@@ -56,6 +58,20 @@ def alg_ops_per_step(est, fields, scheme, level):
     if est == 1:            # approximate
         ops += (2 if fields > 1 else 1) + 2 + coarse
     return ops + 8.0 / (1 << level)
+
+
+def dominant_kernel(stats, Na, Nc):
+    """The timed kernel with the most algorithmic lane-ops per step, and those ops: its
+    works' sample counts (Na for the approximate estimator, Nc otherwise) level by
+    level times the ops per path-step.  Event times are no guide: when the two streams'
+    kernels run concurrently an event pair also spans the time its kernel waits behind
+    the other stream's."""
+    def ops(k):
+        N = Na if k["estimator"] == 1 else Nc
+        return sum(int(N[l]) * (1 << l) * alg_ops_per_step(k["estimator"], k["fields"], k["scheme"], l)
+                   for l in range(LEVELS))
+    dom = max(stats, key=ops)
+    return dom, ops(dom)
 
 
 def peak_valu():
@@ -264,17 +280,9 @@ def main():
     ms_step = dt * 1e3 / args.steps
     value = path_steps / (dt / args.steps)
 
-    # roofline of the dominant kernel: the one with the most algorithmic work per step
-    # (event times are no guide when the two streams' kernels run concurrently: an
-    # event pair also spans the time its kernel waits behind the other stream's)
-    def kernel_ops(k):
-        # algorithmic ops of the kernel's works, level by level (its level mix)
-        N = Na if k["estimator"] == M.EST_APPROX else Nc
-        return sum(int(N[l]) * (1 << l) * alg_ops_per_step(k["estimator"], k["fields"], k["scheme"], l)
-                   for l in range(LEVELS))
-    dom = max(stats, key=kernel_ops)
+    # roofline of the dominant kernel
+    dom, ops = dominant_kernel(stats, Na, Nc)
     per_step_steps = dom["path_steps"] / args.steps
-    ops = kernel_ops(dom)
     # the kernel's time per step (its launches of one step together cover the mix)
     avg_s = dom["ms"] / args.steps * 1e-3
     achieved = ops / avg_s
