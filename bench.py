@@ -33,31 +33,47 @@ EPS = 1e-3                 # price units
 SEED = 1234
 N_PILOT = 100_000
 
-# --- algorithmic VALU work per fine path-step (32-bit lane operations), by kernel
-# class.  Philox4x32-10: 10 rounds of 2 widening 32x32->64 multiplies and 4 xors
-# per block of 4 words; each multiply is weighted by its issue cost relative to a
-# full-rate 32-bit op (MUL64_COST, measured on gfx950 by the instruction probe).
-MUL64_COST = 2.0      # v_mad_u64_u32 issues at half the FP32 rate (probe: 49 vs 98 lanes/CU/clk)
+# --- algorithmic VALU work per fine path-step (32-bit lane operations; a multiply
+# counts one), by kernel class, as the method's own operation counts:
+#   uniform word: a quarter of a Philox4x32-10 call (5 32x32 multiplies for the
+#     high and low halves, ~7.5 xors/adds), shared by the indices packed in it;
+#   table index: 1.5 (shift, mask when packed);
+#   exact inverse normal: ~25 (FP32) or ~60 (FP64, with its logarithm);
+#   fine step: 2 (FP32/FP16/FP64 FMA pair) or 12 (fixed point: product, rounding,
+#     shift, saturation of two operations), Milstein +3 (zsq, zm1, mul3);
+#   coarse step, per fine step (levels >= 1): 1.5 (fixed point 6.5), Milstein +1.5;
+#   Asian / barrier functionals: +1.5 each per fine step;
+#   per path: payoff, level difference and the two sums, ~4 per side.
+PHILOX_WORD_OPS = 12.5
+INDEX_OPS = 1.5
+NORMINV_OPS = {0: 60.0, 1: 25.0}          # arith FP64, FP32
+ARITH_FIXED = 3
 
 
-def philox_ops():
-    return 10 * (2 * MUL64_COST + 4)
-
-
-def alg_ops_per_step(est, fields, scheme, level):
-    """Algorithmic lane-ops per fine path-step of one coupled sample.
-    Table side (FP32, Algorithm 1 per operation): fine step mul + add (2); coarse step
-    per fine pair: zsum, mul1, sum1, mul2, X-add (5), Milstein + zsq, zm1, mul3, sum2 (9);
-    index: shift (+ mask when packed).  Per path: payoff and level difference (~8).
-    The exact-normal estimators count the generator and the payoff only (a lower
-    bound: their inverse normals and FP64 steps are not counted)."""
+def side_step_ops(arith, scheme, level, track=0):
     mil = scheme == 1
-    wpb = 4 * fields
-    ops = philox_ops() / wpb
-    coarse = (9 if mil else 5) / 2.0 if level >= 1 else 0.0
-    if est == 1:            # approximate
-        ops += (2 if fields > 1 else 1) + 2 + coarse
-    return ops + 8.0 / (1 << level)
+    fixed = arith == ARITH_FIXED
+    ops = (12.0 if fixed else 2.0) + (3.0 if mil else 0.0)
+    if level >= 1:
+        ops += (6.5 if fixed else 1.5) + (1.5 if mil else 0.0)
+    return ops + 1.5 * track
+
+
+def alg_ops_per_step(est, fields, scheme, level, arith=1, track=0):
+    """Algorithmic lane-ops per fine path-step of one sample of estimator est
+    (0 plain, 1 approximate, 2 correction); arith: the table side's arithmetic
+    (approximate, correction) or the plain side's (plain).  The correction estimator
+    runs the FP64 exact side and the table side on one word per step."""
+    per_path = 4.0
+    if est == 1:
+        ops = PHILOX_WORD_OPS / fields + INDEX_OPS + side_step_ops(arith, scheme, level, track)
+    elif est == 2:
+        ops = (PHILOX_WORD_OPS + INDEX_OPS + NORMINV_OPS[0] + side_step_ops(0, scheme, level, track)
+               + side_step_ops(arith, scheme, level, track))
+        per_path = 8.0
+    else:
+        ops = PHILOX_WORD_OPS + NORMINV_OPS[0 if arith == 0 else 1] + side_step_ops(arith, scheme, level, track)
+    return ops + per_path / (1 << level)
 
 
 def dominant_kernel(stats, Na, Nc):
@@ -68,7 +84,8 @@ def dominant_kernel(stats, Na, Nc):
     the other stream's."""
     def ops(k):
         N = Na if k["estimator"] == 1 else Nc
-        return sum(int(N[l]) * (1 << l) * alg_ops_per_step(k["estimator"], k["fields"], k["scheme"], l)
+        return sum(int(N[l]) * (1 << l) * alg_ops_per_step(k["estimator"], k["fields"], k["scheme"], l,
+                                                           k.get("arith", 1), k.get("track", 0))
                    for l in range(LEVELS))
     dom = max(stats, key=ops)
     return dom, ops(dom)
