@@ -178,6 +178,8 @@ typedef struct mlmc_context mlmc_context;
 mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t workspace_bytes,
                                 void* stream, mlmc_context** out);
 void mlmc_context_destroy(mlmc_context* ctx);
+/* The context's last error message; with ctx NULL, the calling thread's last
+ * error of a context-free call (mlmc_level_sums_static). */
 const char* mlmc_last_error(const mlmc_context* ctx);
 const char* mlmc_status_string(int32_t status);
 int32_t mlmc_abi_version(void);
@@ -235,6 +237,35 @@ mlmc_status mlmc_level_sums_enqueue(mlmc_context* ctx, uint32_t n, const mlmc_le
  * ticket is waited on once; MLMC_E_UNKNOWN_TICKET for a ticket never issued or
  * already waited on. */
 mlmc_status mlmc_level_sums_wait(mlmc_context* ctx, uint64_t ticket);
+
+/* For callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  The sums of mlmc_level_sums for one
+ * (level, estimator) path range without a context and without allocating: no
+ * hipMalloc / hipFree, no pinned host memory, no stream or event, no library call
+ * that allocates.  The plan and the per-tile partial sums live in a 4 MiB device
+ * array inside the library, one per GPU, held until the process ends; the plan
+ * reaches it as kernel arguments.  Every launch goes to `stream` (a hipStream_t on
+ * the current device; NULL: the null stream) and the call returns without
+ * waiting.
+ *   prob, level, n_paths, path_offset, prec, estimator, seed, option_id: as
+ *     mlmc_level_sums (host structs, read before the call returns).
+ *   out_dev: DEVICE array of popcount(payoff_mask) mlmc_sums, in increasing payoff
+ *     order, caller-owned; written by the stream's last kernel of the call.
+ * The launch geometry is the library's default (mlmc_tuning defaults); the sums
+ * equal mlmc_level_sums' under that geometry while the work needs at most 8192
+ * tiles (larger works are split into 8192 tiles: integer sums are unchanged, FP64
+ * sums may differ in rounding), without per-path debug records.
+ * All calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  Nothing in
+ * the array has to start at zero (every partial sum is written before it is read).
+ * Errors: MLMC_E_INVALID (validation as mlmc_level_sums; out_dev NULL),
+ * MLMC_E_NOMEM (the plan and partial sums exceed the 4 MiB array), MLMC_E_DEVICE
+ * (a HIP call failed).  The message is mlmc_last_error(NULL) on the calling
+ * thread. */
+mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t level, uint64_t n_paths,
+                                   uint64_t path_offset, const mlmc_precision* prec,
+                                   int32_t estimator, uint64_t seed, uint32_t option_id,
+                                   void* stream, mlmc_sums* out_dev);
 
 /* Kernel timing.  With timing on, every path-kernel launch is bracketed by HIP
  * events on the context's stream; per kernel class the library accumulates the

@@ -16,7 +16,7 @@ from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, LEVELWORK_DTYPE, PAYO
                    RunConfig, ServerConfig, ServerStats, Sums, Tuning, WidthPlan, check, error_model_struct, lib,
                    make_precision, make_problem, make_run_config)
 
-__all__ = ["Context", "make_problem", "make_precision", "make_run_config", "build_table",
+__all__ = ["Context", "level_sums_static", "make_problem", "make_precision", "make_run_config", "build_table",
            "stream_words", "check_paths_host", "allocate", "validate", "optimise_widths", "MlmcError",
            "EST_PLAIN", "EST_APPROX", "EST_CORR", "PAYOFFS", "VARS", "RECORD_DTYPE", "SUMS_DTYPE",
            "SumsBatch"]
@@ -258,6 +258,40 @@ class SumsBatch:
 
 
 # ---------------------------------------------------------- host-side helpers
+def level_sums_static(problem, level, n_paths, path_offset, prec, estimator, seed, option=0,
+                      out=None, stream=None):
+    """mlmc_level_sums_static: the sums of one level into `out`, a device tensor of at
+    least popcount(mask) * SUMS_DTYPE.itemsize bytes (allocated here when None), on
+    `stream` (default: the current torch stream), without waiting.  Returns `out`;
+    sums_from_device(out, problem) reads it after the stream has reached it."""
+    import torch
+    names = _payoff_names(problem)
+    if out is None:
+        out = torch.empty(len(names) * SUMS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    if out.numel() * out.element_size() < len(names) * SUMS_DTYPE.itemsize or not out.is_cuda:
+        raise ValueError("out: device tensor too small")
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    status = lib().mlmc_level_sums_static(C.byref(problem), level, int(n_paths), int(path_offset),
+                                          C.byref(prec), estimator, int(seed), option,
+                                          C.c_void_p(st.cuda_stream), C.c_void_p(out.data_ptr()))
+    if status != 0:
+        raise MlmcError(status, lib().mlmc_last_error(None).decode())
+    return out
+
+
+def sums_from_device(out, problem):
+    """{payoff: sums dict} from a device tensor written by level_sums_static."""
+    names = _payoff_names(problem)
+    raw = out.detach().cpu().numpy().tobytes()[:len(names) * SUMS_DTYPE.itemsize]
+    arr = np.frombuffer(raw, dtype=SUMS_DTYPE)
+    res = {}
+    for i, nm in enumerate(names):
+        d = {f: arr[i][f].item() for f in SUMS_DTYPE.names}
+        d["isum2"] = (int(d["isum2_hi"]) << 64) | int(d["isum2_lo"])
+        res[nm] = d
+    return res
+
+
 def optimise_widths(model, c_rng=1e4, rng_term=False):
     """Section 6 widths of one level from an error model (dict as Context.error_model
     returns); host only."""

@@ -202,6 +202,7 @@ def lib():
         "mlmc_context_destroy": (None, [vp]),
         "mlmc_level_sums": (st, [vp, P(Problem), i32, u64, u64, P(Precision), i32, u64, u32,
                                  P(Sums), vp]),
+        "mlmc_level_sums_static": (st, [P(Problem), i32, u64, u64, P(Precision), i32, u64, u32, vp, vp]),
         "mlmc_level_sums_batch": (st, [vp, u32, P(LevelWork)]),
         "mlmc_level_sums_enqueue": (st, [vp, u32, P(LevelWork), P(u64)]),
         "mlmc_level_sums_wait": (st, [vp, u64]),
@@ -238,7 +239,7 @@ def lib():
 
 
 EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_context_create",
-            "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_batch",
+            "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_static", "mlmc_level_sums_batch",
             "mlmc_level_sums_enqueue", "mlmc_level_sums_wait", "mlmc_set_timing",
             "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",

@@ -17,8 +17,8 @@ BUILD = os.path.join(os.path.dirname(PKG), "_build")
 LIB = os.path.join(PKG, "libmlmc.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "host_check.hip", "errmodel.hip", "runtime.cpp", "server.cpp", "host/prepare.cpp",
-           "host/widths.cpp"]
+SOURCES = ["kernels.hip", "host_check.hip", "errmodel.hip", "static_entry.hip", "runtime.cpp", "server.cpp",
+           "host/prepare.cpp", "host/widths.cpp"]
 
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Wno-unused-variable",

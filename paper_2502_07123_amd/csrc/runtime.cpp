@@ -132,6 +132,45 @@ void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
 }
 }  // namespace
 
+uint32_t block_for(const Tuning& t, const Variant& v, const VariantInfo& vi) {
+    return std::min<uint32_t>(vi.tab_bytes && v.est == MLMC_EST_APPROX ? t.block_table : t.block_exact,
+                              static_cast<uint32_t>(vi.max_block));
+}
+
+// Groups per tile: about tile_steps path-steps, but small enough that the work alone
+// has min_tiles tiles (parallelism), and at most max_tiles tiles; a function of the
+// work and the geometry alone, so a work's sums do not depend on its neighbours.
+WorkSplit split_work(const Tuning& t, uint32_t block, uint64_t S, int level, uint64_t path_begin, uint64_t n,
+                     uint64_t max_tiles) {
+    WorkSplit sp;
+    const uint64_t G = S >> level;                             // paths per group
+    sp.g0 = path_begin / G;
+    sp.g1 = (path_begin + n - 1) / G + 1;
+    const uint64_t total = sp.g1 - sp.g0;
+    uint64_t ppt = std::max<uint64_t>(1, t.tile_steps / (block * S));
+    const uint64_t fill = (total + uint64_t(block) * t.min_tiles - 1) / (uint64_t(block) * t.min_tiles);
+    ppt = std::max<uint64_t>(1, std::min(ppt, fill));
+    sp.per = uint64_t(block) * ppt;
+    if ((total + sp.per - 1) / sp.per > max_tiles) sp.per = (total + max_tiles - 1) / max_tiles;
+    sp.nt = (total + sp.per - 1) / sp.per;
+    return sp;
+}
+
+// LDS of a work: its step table, plus the level-0 index histogram of the approximate
+// estimator or (FP32, small enough) its per-index sample table, or the correction
+// estimator's per-index approximate-side samples (float table side).
+uint32_t lds_bytes_for(const Variant& v, const LevelDev& L) {
+    uint32_t extra = 0;
+    const uint32_t ys = static_cast<uint32_t>(v.np) * L.table_entries;
+    if (v.est == MLMC_EST_APPROX) {
+        extra = 4u * L.table_entries;
+        if (v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) extra = std::max(extra, 8u * ys);
+    } else if (v.est == MLMC_EST_CORR && v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) {
+        extra = 8u * ys;
+    }
+    return L.table_bytes + extra;
+}
+
 // Waits for a flight, copies its results (to out, or to the mlmc_sums of its
 // enqueued work list) and returns its staging buffer and events to the pools.
 mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out) {
@@ -280,9 +319,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         LaunchGroup& g = kv.second;
         g.vi = variant_info(g.v);
         if (!g.vi.fn) return fail(ctx, MLMC_E_INVALID, "no compiled kernel for this estimator/arithmetic/packing");
-        g.block = std::min<uint32_t>(g.vi.tab_bytes && g.v.est == MLMC_EST_APPROX ? ctx->tune.block_table
-                                                                                  : ctx->tune.block_exact,
-                                     static_cast<uint32_t>(g.vi.max_block));
+        g.block = block_for(ctx->tune, g.v, g.vi);
         g.w0 = static_cast<uint32_t>(wtiles.size());
         for (uint32_t wi : g.works) {
             const WorkSpec& w = works[wi];
@@ -314,26 +351,13 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             }
             // a buffered work's group is one path
             const uint64_t S = zb ? N : group_span(w.level, static_cast<uint32_t>(g.vi.wpb));
-            const uint64_t G = S >> w.level;                       // paths per group
-            const uint64_t g0 = w.path_begin / G;
-            const uint64_t g1 = (w.path_begin + w.n - 1) / G + 1;
-            // groups per tile: about tile_steps path-steps, but small enough that the work
-            // alone has min_tiles tiles (parallelism), and at most max_tiles tiles; a
-            // function of the work alone, so a work's sums do not depend on its neighbours
-            const uint64_t total = g1 - g0;
-            uint64_t ppt = std::max<uint64_t>(1, ctx->tune.tile_steps / (g.block * S));
-            const uint64_t fill = (total + uint64_t(g.block) * ctx->tune.min_tiles - 1) /
-                                  (uint64_t(g.block) * ctx->tune.min_tiles);
-            ppt = std::max<uint64_t>(1, std::min(ppt, fill));
-            uint64_t per = uint64_t(g.block) * ppt;
-            const uint64_t max_tiles = 1u << 16;
-            if ((total + per - 1) / per > max_tiles) per = (total + max_tiles - 1) / max_tiles;
-            const uint64_t nt = (total + per - 1) / per;
+            const WorkSplit sp = split_work(ctx->tune, g.block, S, w.level, w.path_begin, w.n, FLIGHT_MAX_TILES);
+            const uint64_t nt = sp.nt;
             if (uint64_t(n_slots) + nt >= (uint64_t(1) << 31)) return fail(ctx, MLMC_E_NOMEM, "too many tiles");
             WorkTilesDev wt;
-            wt.g0 = g0;
-            wt.g1 = g1;
-            wt.per = per;
+            wt.g0 = sp.g0;
+            wt.g1 = sp.g1;
+            wt.per = sp.per;
             wt.work = wi;
             wt.tile_end = g.n_tiles + static_cast<uint32_t>(nt);
             wt.slot_begin = n_slots;
@@ -350,16 +374,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             // table, plus the level-0 index histogram of the approximate estimator or
             // (FP32, small enough) its per-index sample table, or the correction
             // estimator's per-index approximate-side samples (float table side)
-            const LevelDev& Lw = levels[wdev[wi].lvl];
-            uint32_t extra = 0;
-            const uint32_t ys = static_cast<uint32_t>(g.v.np) * Lw.table_entries;
-            if (g.v.est == MLMC_EST_APPROX) {
-                extra = 4u * Lw.table_entries;
-                if (g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) extra = std::max(extra, 8u * ys);
-            } else if (g.v.est == MLMC_EST_CORR && g.v.arith != MLMC_ARITH_FIXED && ys <= YTAB_MAX_ENTRIES) {
-                extra = 8u * ys;                  // the level-0 approximate-side samples
-            }
-            g.lds = std::max<uint32_t>(g.lds, Lw.table_bytes + extra);
+            g.lds = std::max<uint32_t>(g.lds, lds_bytes_for(g.v, levels[wdev[wi].lvl]));
         }
         g.w1 = static_cast<uint32_t>(wtiles.size());
     }
@@ -903,7 +918,7 @@ const char* mlmc_status_string(int32_t s) {
     }
 }
 
-const char* mlmc_last_error(const mlmc_context* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+const char* mlmc_last_error(const mlmc_context* ctx) { return ctx ? ctx->err.c_str() : mlmc::static_last_error(); }
 
 mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t workspace_bytes, void* stream,
                                 mlmc_context** out) {

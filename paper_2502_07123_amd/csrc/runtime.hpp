@@ -39,6 +39,24 @@ struct Tuning {
     uint64_t overlap_min_steps = uint64_t(1) << 26;
 };
 
+// The calling thread's last error message of mlmc_level_sums_static ("" if none).
+const char* static_last_error();
+
+// Threads per block of a kernel variant under a geometry.
+uint32_t block_for(const Tuning& t, const Variant& v, const VariantInfo& vi);
+
+// The tiles of one work: groups [g0, g1) (S stream positions each) in nt tiles of
+// `per` groups.
+struct WorkSplit {
+    uint64_t g0, g1, per, nt;
+};
+constexpr uint64_t FLIGHT_MAX_TILES = uint64_t(1) << 16;
+WorkSplit split_work(const Tuning& t, uint32_t block, uint64_t S, int level, uint64_t path_begin, uint64_t n,
+                     uint64_t max_tiles);
+
+// Dynamic LDS bytes the path kernel of variant v needs for level L.
+uint32_t lds_bytes_for(const Variant& v, const LevelDev& L);
+
 // One (option, level, estimator) path range of a launch.
 struct WorkSpec {
     const mlmc_problem* prob;

@@ -192,3 +192,18 @@ def test_allocation_equals_oracle():
         got = M.allocate(V, Cst, 1e-7, theta)
         ref = optimal_samples(V, Cst, 1e-7, theta)
         assert np.array_equal(got.astype(np.int64), ref)
+
+
+def test_static_entry_validates_before_any_device_call():
+    prob = M.make_problem("euler", ("euro",))
+    prec = M.make_precision("fp32", 8)
+    L = _lib.lib()
+    bad = M.make_problem("euler", ("euro",), sigma=-1.0)
+    st = L.mlmc_level_sums_static(C.byref(bad), 2, 100, 0, C.byref(prec), M.EST_APPROX, 1, 0, None,
+                                  C.c_void_p(8))
+    assert st == -1 and L.mlmc_last_error(None).decode()
+    st = L.mlmc_level_sums_static(C.byref(prob), 2, 0, 0, C.byref(prec), M.EST_APPROX, 1, 0, None,
+                                  C.c_void_p(8))
+    assert st == -1
+    st = L.mlmc_level_sums_static(C.byref(prob), 2, 100, 0, C.byref(prec), M.EST_APPROX, 1, 0, None, None)
+    assert st == -1 and "out_dev" in L.mlmc_last_error(None).decode()
