@@ -95,7 +95,7 @@ typedef struct mlmc_problem {
  * or of the PLAIN generator.
  *   arith        PLAIN: FP64 or FP32 (exact normals in that precision).
  *                APPROX/CORR: FP32, FP16 or FIXED with Method-1 table normals;
- *                the exact side of CORR is always FP64 with FP64 normals.  FP32
+ *                the exact side of CORR is set by exact_side.  FP32
  *                and FP16 evaluate Algorithm 1 operation by operation, each result
  *                rounded to the type (IEEE nearest-even, no fused multiply-add);
  *                constants and k, b are rounded once from their FP64 values.
@@ -121,7 +121,13 @@ typedef struct mlmc_problem {
  *                3: Method 3, piecewise linear on the q - 1 dyadic intervals of
  *                the magnitude bits).  The library expands Methods 2 and 3 into the
  *                2^q-entry table (values formed in FP64, then rounded once to the
- *                side's format).  PLAIN: must be 0 or 1. */
+ *                side's format).  PLAIN: must be 0 or 1.
+ *   exact_side   CORR: the exact side's arithmetic (Section 2.2's full-precision
+ *                path on the same uniforms).  0: FP64 arithmetic with the FP64
+ *                inverse normal (the paper's "double" increment); 1: FP32 Algorithm 1
+ *                arithmetic with the FP32 inverse normal, as the plain-FP32
+ *                estimator (FP64 then holds only the sums); needs an FP32 or FP16
+ *                table side.  Other estimators: 0 or 1, ignored. */
 typedef struct mlmc_precision {
     uint32_t struct_size;
     int32_t arith;
@@ -130,7 +136,7 @@ typedef struct mlmc_precision {
     int32_t word_bits[MLMC_NVARS];
     int32_t frac_bits[MLMC_NVARS];
     int32_t rng_method;
-    int32_t reserved;
+    int32_t exact_side;
 } mlmc_precision;
 
 /* Sums of one (level, estimator, payoff) over a set of paths (Section 2.1:
@@ -272,7 +278,9 @@ mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t level, uint
  * launches, the summed event time and the fine path-steps processed. */
 typedef struct mlmc_kernel_stat {
     int32_t estimator, arith, scheme, fields;  /* fields: indices per 32-bit word */
-    int32_t payoffs, track, pad0, pad1;
+    int32_t payoffs, track;
+    int32_t level0;                            /* 1: the level-0 kernel of an exact-normal estimator */
+    int32_t exact32;                           /* 1: correction estimator with an FP32 exact side */
     uint64_t launches;
     double ms;                                 /* summed event time */
     uint64_t path_steps;                       /* fine path-steps (paths * 2^level) */
@@ -371,6 +379,10 @@ typedef struct mlmc_result {
     double seconds;             /* wall time of the estimate */
     uint64_t path_steps;        /* fine path-steps generated, all estimators */
     uint64_t saturations;
+    int32_t exact_sides;        /* samples in the estimate: bit 0 correction with an FP64
+                                   exact side, bit 1 correction with an FP32 exact side,
+                                   bit 2 plain samples (plain_arith) */
+    int32_t pad;
     mlmc_level_stats level[MLMC_MAX_LEVELS];
 } mlmc_result;
 
@@ -516,6 +528,65 @@ typedef struct mlmc_width_plan {
 mlmc_status mlmc_optimise_widths(const mlmc_error_model* model, double c_rng, int32_t rng_term,
                                  mlmc_width_plan* out);
 
+/* The exact normal of the coupled pair (Section 3.1): Z = Phi^-1(U) with
+ * U = 2^-32 (J + 1/2), for n 32-bit words, by the path kernels' own inverse normal
+ * (the four-wide form the exact-normal loops use, on groups of four; a ragged
+ * tail with the scalar form).  J_dev: device array of n uint32; out_dev: device
+ * array of n doubles (arith MLMC_ARITH_FP64) or floats (MLMC_ARITH_FP32).
+ * Synchronous on the context's stream.  Errors: MLMC_E_INVALID (arith, NULL
+ * buffers), MLMC_E_DEVICE. */
+mlmc_status mlmc_inverse_normal(mlmc_context* ctx, const uint32_t* J_dev, uint64_t n, int32_t arith,
+                                void* out_dev);
+
+/* The low-precision side of one level chosen by Section 6's level objective, with
+ * the cost of Section 5 measured in gfx950 issue cycles instead of FPGA bit
+ * operations.  Issue rates of the instruction classes the path kernels use, in
+ * wave-instructions per CU per clock (an instruction's issue cost is the reciprocal):
+ * FP32/FP16 arithmetic, 32-bit integer, FP64 FMA and add, 32x32->64 multiply-add,
+ * random 8-byte and 4-byte LDS reads. */
+typedef struct mlmc_gpu_rates {
+    uint32_t struct_size;
+    uint32_t pad;
+    double f32, i32, f64_fma, f64_add, u64_mad, lds_b64, lds_b32;
+} mlmc_gpu_rates;
+
+/* The rates measured on one MI355X by the issue-rate probe.  out->struct_size must
+ * be set. */
+mlmc_status mlmc_gpu_rates_default(mlmc_gpu_rates* out);
+
+/* Cost per fine path-step (CU issue cycles per 64 path-steps) of the approximate
+ * estimator (Philox word share, index, table read, the side's fine step and half a
+ * coarse step, the per-path payoff and sums over 2^level steps) and of the
+ * correction estimator (one word per step, the FP64 inverse normal and FP64 steps,
+ * the table side unpacked), for a table side (arith FP32 / FP16 / FIXED, q, packed)
+ * at `level`.  Host only.  Errors: MLMC_E_INVALID, MLMC_E_VERSION. */
+mlmc_status mlmc_side_costs(int32_t arith, int32_t table_bits, int32_t packed, int32_t scheme,
+                            int32_t level, const mlmc_gpu_rates* rates, double* c_approx, double* c_corr);
+
+typedef struct mlmc_level_choice {
+    uint32_t struct_size;
+    int32_t level, arith, table_bits, packed;
+    int32_t pad;
+    double v_approx, v_corr;     /* V~ (= V_level) and the modelled V^D */
+    double c_approx, c_corr;     /* 2^level times the costs per fine path-step */
+    double objective;            /* sqrt(V~ C~) + sqrt(V^D C^D) of the choice */
+    double objective_fp32_q8;    /* the same for FP32 with q = 8 packed indices */
+} mlmc_level_choice;
+
+/* Section 6's level objective sqrt(V~ C~) + sqrt(V^D C^D) minimised over the table
+ * sides FP32 with q = 8, 6, 4 (packed) and 10, 12; FP16 with q = 8, 7 (packed) and
+ * 10; and, when fixed_formats is given, FIXED with those formats and q = 8, 10, 12
+ * (the first minimum in that order wins).  V~ = model->V_level; V^D = the linear
+ * rounding model (1/12) sum_v S_v 4^(e_v - d_v) with d = the significand bits (FP32
+ * 24, FP16 11) or w - 1 of the fixed formats, plus S_Z MSE_q (the Method-1 table of
+ * q bits, Section 4.3, without the 1/12); C~, C^D = 2^level mlmc_side_costs.
+ * out: the chosen precision (rng_method 1, exact_side 0; fixed: fixed_formats' widths);
+ * info (NULL allowed): the numbers behind it.  struct_size of every struct must be
+ * set.  Host only.  Errors: MLMC_E_INVALID, MLMC_E_VERSION. */
+mlmc_status mlmc_choose_precision(const mlmc_error_model* model, const mlmc_gpu_rates* rates,
+                                  const mlmc_precision* fixed_formats, mlmc_precision* out,
+                                  mlmc_level_choice* info);
+
 /* ------------------------------------------------- host-side helpers (no GPU) */
 
 /* Method-1 table (Section 3.1): T_q[k] = 2^q (phi(Phi^-1(k 2^-q)) -
@@ -559,6 +630,10 @@ mlmc_status mlmc_check_paths_host(const mlmc_problem* prob, int32_t level, uint6
                                   uint64_t path_offset, const mlmc_precision* prec,
                                   int32_t estimator, uint64_t seed, uint32_t option_id,
                                   mlmc_sums* out, mlmc_path_record* records);
+
+/* mlmc_inverse_normal with the kernels' code compiled for the host (FP32: the
+ * host's logarithm in place of the device's): host arrays J[n] and out[n]. */
+mlmc_status mlmc_inverse_normal_host(const uint32_t* J, uint64_t n, int32_t arith, void* out);
 
 /* Sample allocation (Section 2.1 / 2.2) as used by the drivers:
  * N_i = ceil(theta^-1 eps2^-1 sqrt(V_i / C_i) sum_j sqrt(V_j C_j)) over the m

@@ -44,6 +44,9 @@ Estimators (Section 2.2):
   plain (0)       Y = P_f - P_c on the exact side.
   approx (1)      Y~ = P~_f - P~_c on the low-precision side with table normals.
   correction (2)  Y_D = (P_f - P_c) - Y~ with both sides driven by the same J.
+The correction's exact side is FP64 with FP64 normals (reading R21: the paper's
+"double" increment), or, with Precision.exact = 'fp32', FP32 arithmetic with the
+exact normal rounded to FP32 (the narrower reading: FP64 only for the sums).
 
 This module is test infrastructure: see the package docstring.
 """
@@ -85,6 +88,7 @@ class Precision:
     packed: bool = False         # approx estimator: floor(32/q) indices per word
     fmt: tuple = ()              # tuple of (var, w, f) for 'fixed'
     method: int = 1              # approximate normals: Method 1, 2 (n = 2) or 3
+    exact: str = "fp64"          # correction estimator's exact side: fp64 or fp32 (R21)
 
     def fmt_of(self, var):
         for v, w, f in self.fmt:
@@ -360,7 +364,7 @@ def simulate(prob: Problem, level: int, paths, prec: Precision, estimator: int,
 
     exact_side = approx_side = None
     if estimator in (EST_PLAIN, EST_CORR):
-        exact_side = PathState(make_side(plain_arith if estimator == EST_PLAIN else "fp64",
+        exact_side = PathState(make_side(plain_arith if estimator == EST_PLAIN else prec.exact,
                                          prec, c, prob.scheme), n, level)
     if estimator in (EST_APPROX, EST_CORR):
         approx_side = PathState(make_side(prec.arith, prec, c, prob.scheme), n, level)

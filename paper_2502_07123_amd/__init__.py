@@ -19,6 +19,7 @@ from ._lib import (ARITH, EST_APPROX, EST_CORR, EST_PLAIN, LEVELWORK_DTYPE, PAYO
 __all__ = ["Context", "level_sums_static", "make_problem", "make_precision", "make_run_config", "build_table",
            "stream_words", "check_paths_host", "allocate", "validate", "optimise_widths", "MlmcError",
            "EST_PLAIN", "EST_APPROX", "EST_CORR", "PAYOFFS", "VARS", "RECORD_DTYPE", "SUMS_DTYPE",
+    "gpu_rates", "side_costs", "choose_precision", "inverse_normal_host", "level_sums_static",
            "SumsBatch"]
 
 
@@ -175,6 +176,17 @@ class Context:
         return [(tk[i], res[i].as_dict()) for i in range(n.value)]
 
     # ---- rounding-error model and bit widths (Sections 4-6)
+    def inverse_normal(self, J, arith="fp64"):
+        """Phi^-1((J + 1/2) 2^-32) by the kernels' inverse normal: J a uint32 numpy
+        array (or device tensor of int32 bits); returns a numpy array."""
+        import torch
+        Jt = torch.as_tensor(np.asarray(J, dtype=np.uint32).view(np.int32)).to(f"cuda:{self.device}")
+        dt = torch.float64 if arith == "fp64" else torch.float32
+        out = torch.empty(Jt.numel(), dtype=dt, device=f"cuda:{self.device}")
+        check(lib().mlmc_inverse_normal(self.h, C.c_void_p(Jt.data_ptr()), Jt.numel(), ARITH[arith],
+                                        C.c_void_p(out.data_ptr())), self.h)
+        return out.cpu().numpy()
+
     def error_model(self, problem, level, n_paths, q, seed, option=0):
         m = ErrorModel()
         m.struct_size = C.sizeof(ErrorModel)
@@ -290,6 +302,51 @@ def sums_from_device(out, problem):
         d["isum2"] = (int(d["isum2_hi"]) << 64) | int(d["isum2_lo"])
         res[nm] = d
     return res
+
+
+def gpu_rates(**over):
+    """The measured issue rates (mlmc_gpu_rates_default), fields overridden by `over`."""
+    from ._lib import GpuRates
+    r = GpuRates()
+    r.struct_size = C.sizeof(GpuRates)
+    check(lib().mlmc_gpu_rates_default(C.byref(r)))
+    for k, v in over.items():
+        setattr(r, k, v)
+    return r
+
+
+def side_costs(arith, q, packed, scheme, level, rates=None):
+    """(c_approx, c_corr) per fine path-step of a table side (mlmc_side_costs)."""
+    a, c = C.c_double(), C.c_double()
+    r = rates if rates is not None else gpu_rates()
+    check(lib().mlmc_side_costs(ARITH[arith], q, 1 if packed else 0, 0 if scheme == "euler" else 1, level,
+                                C.byref(r), C.byref(a), C.byref(c)))
+    return a.value, c.value
+
+
+def choose_precision(model, rates=None, fixed_fmt=None):
+    """mlmc_choose_precision for one level's error model (a mapping as returned by
+    Context.error_model); fixed_fmt: var -> (w, f) formats of the FIXED candidate.
+    Returns (Precision, info dict)."""
+    from ._lib import LevelChoice
+    m = model if isinstance(model, ErrorModel) else error_model_struct(model)
+    r = rates if rates is not None else gpu_rates()
+    ff = make_precision("fixed", 8, False, fixed_fmt) if fixed_fmt else None
+    out = make_precision("fp32", 8)
+    info = LevelChoice()
+    info.struct_size = C.sizeof(LevelChoice)
+    check(lib().mlmc_choose_precision(C.byref(m), C.byref(r), C.byref(ff) if ff is not None else None,
+                                      C.byref(out), C.byref(info)))
+    return out, info.as_dict()
+
+
+def inverse_normal_host(J, arith="fp64"):
+    """mlmc_inverse_normal_host: the kernels' inverse normal compiled for the host."""
+    J = np.ascontiguousarray(np.asarray(J, dtype=np.uint32))
+    out = np.empty(J.size, dtype=np.float64 if arith == "fp64" else np.float32)
+    check(lib().mlmc_inverse_normal_host(J.ctypes.data_as(C.c_void_p), J.size, ARITH[arith],
+                                         out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def optimise_widths(model, c_rng=1e4, rng_term=False):

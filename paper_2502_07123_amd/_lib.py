@@ -43,7 +43,7 @@ class Problem(C.Structure):
 class Precision(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("arith", C.c_int32), ("table_bits", C.c_int32),
                 ("packed", C.c_int32), ("word_bits", C.c_int32 * NVARS),
-                ("frac_bits", C.c_int32 * NVARS), ("rng_method", C.c_int32), ("reserved", C.c_int32)]
+                ("frac_bits", C.c_int32 * NVARS), ("rng_method", C.c_int32), ("exact_side", C.c_int32)]
 
 
 class Sums(C.Structure):
@@ -83,7 +83,7 @@ class LevelWork(C.Structure):
 class KernelStat(C.Structure):
     _fields_ = [("estimator", C.c_int32), ("arith", C.c_int32), ("scheme", C.c_int32),
                 ("fields", C.c_int32), ("payoffs", C.c_int32), ("track", C.c_int32),
-                ("pad0", C.c_int32), ("pad1", C.c_int32), ("launches", C.c_uint64),
+                ("level0", C.c_int32), ("exact32", C.c_int32), ("launches", C.c_uint64),
                 ("ms", C.c_double), ("path_steps", C.c_uint64)]
 
     def as_dict(self):
@@ -116,14 +116,15 @@ class Result(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("status", C.c_int32), ("L", C.c_int32),
                 ("sweeps", C.c_int32), ("estimate", C.c_double), ("variance", C.c_double),
                 ("seconds", C.c_double), ("path_steps", C.c_uint64), ("saturations", C.c_uint64),
-                ("level", LevelStats * MAX_LEVELS)]
+                ("exact_sides", C.c_int32), ("pad", C.c_int32), ("level", LevelStats * MAX_LEVELS)]
 
     def as_dict(self):
         lv = [{"n": list(self.level[l].n), "mean": list(self.level[l].mean),
                "var": list(self.level[l].var)} for l in range(self.L + 1)]
         return {"status": self.status, "L": self.L, "sweeps": self.sweeps,
                 "estimate": self.estimate, "variance": self.variance, "seconds": self.seconds,
-                "path_steps": self.path_steps, "saturations": self.saturations, "levels": lv}
+                "path_steps": self.path_steps, "saturations": self.saturations,
+                "exact_sides": self.exact_sides, "levels": lv}
 
 
 class ServerConfig(C.Structure):
@@ -166,6 +167,22 @@ def error_model_struct(d):
         for i in range(NVARS):
             arr[i] = d[k][i]
     return m
+
+
+class GpuRates(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("pad", C.c_uint32), ("f32", C.c_double), ("i32", C.c_double),
+                ("f64_fma", C.c_double), ("f64_add", C.c_double), ("u64_mad", C.c_double),
+                ("lds_b64", C.c_double), ("lds_b32", C.c_double)]
+
+
+class LevelChoice(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("level", C.c_int32), ("arith", C.c_int32),
+                ("table_bits", C.c_int32), ("packed", C.c_int32), ("pad", C.c_int32),
+                ("v_approx", C.c_double), ("v_corr", C.c_double), ("c_approx", C.c_double),
+                ("c_corr", C.c_double), ("objective", C.c_double), ("objective_fp32_q8", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("struct_size", "pad")}
 
 
 class ServerStats(C.Structure):
@@ -228,6 +245,11 @@ def lib():
         "mlmc_check_paths_host": (st, [P(Problem), i32, u64, u64, P(Precision), i32, u64, u32,
                                        P(Sums), vp]),
         "mlmc_allocate": (st, [u32, P(C.c_double), P(C.c_double), C.c_double, C.c_double, P(u64)]),
+        "mlmc_inverse_normal": (st, [vp, vp, u64, i32, vp]),
+        "mlmc_gpu_rates_default": (st, [P(GpuRates)]),
+        "mlmc_side_costs": (st, [i32, i32, i32, i32, i32, P(GpuRates), P(C.c_double), P(C.c_double)]),
+        "mlmc_choose_precision": (st, [P(ErrorModel), P(GpuRates), P(Precision), P(Precision), P(LevelChoice)]),
+        "mlmc_inverse_normal_host": (st, [vp, u64, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -246,7 +268,8 @@ EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_c
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_poll_done", "mlmc_server_stats_get",
             "mlmc_server_stop", "mlmc_error_model_compute", "mlmc_optimise_widths",
             "mlmc_build_table", "mlmc_build_rng_table", "mlmc_stream_words", "mlmc_validate", "mlmc_check_paths_host",
-            "mlmc_allocate")
+            "mlmc_allocate", "mlmc_inverse_normal", "mlmc_inverse_normal_host", "mlmc_gpu_rates_default",
+            "mlmc_side_costs", "mlmc_choose_precision")
 
 
 # ------------------------------------------------------------------ builders
@@ -259,15 +282,16 @@ def make_problem(scheme="euler", payoffs=("euro",), S0=100.0, K=100.0, r=0.05, s
                    S0, K, r, sigma, T, barrier)
 
 
-def make_precision(arith="fp32", q=8, packed=False, fmt=None, method=1):
+def make_precision(arith="fp32", q=8, packed=False, fmt=None, method=1, exact="fp64"):
     """fmt: mapping var -> (word_bits, frac_bits) for 'fixed'; method: approximate
-    normals of Section 3 (1, 2 or 3)."""
+    normals of Section 3 (1, 2 or 3); exact: the correction's exact side (fp64/fp32)."""
     p = Precision()
     p.struct_size = C.sizeof(Precision)
     p.arith = ARITH[arith]
     p.table_bits = q
     p.packed = 1 if packed else 0
     p.rng_method = method
+    p.exact_side = 0 if exact == "fp64" else 1
     if fmt:
         for v, (w, f) in dict(fmt).items():
             i = VARS.index(v)

@@ -2,6 +2,7 @@
 directory with hipcc.
 
     python -m paper_2502_07123_amd.build         # or build() from Python
+    python -m paper_2502_07123_amd.build --probe # also the issue-rate probe executable
 
 Always recompiles (objects go to _build/ next to the package).
 """
@@ -17,8 +18,8 @@ BUILD = os.path.join(os.path.dirname(PKG), "_build")
 LIB = os.path.join(PKG, "libmlmc.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "host_check.hip", "errmodel.hip", "static_entry.hip", "runtime.cpp", "server.cpp",
-           "host/prepare.cpp", "host/widths.cpp"]
+SOURCES = ["kernels.hip", "host_check.hip", "errmodel.hip", "static_entry.hip", "inverse_normal.hip", "runtime.cpp", "server.cpp",
+           "host/prepare.cpp", "host/widths.cpp", "host/choose.cpp"]
 
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Wno-unused-variable",
@@ -59,7 +60,8 @@ def build_probe(hipcc):
     return PROBE
 
 
-def build(verbose=False):
+def build(verbose=False, probe=False):
+    """The library; with probe, also the issue-rate probe (measurement runs only)."""
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
@@ -75,9 +77,10 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, LIB)
-    build_probe(hipcc)
+    if probe:
+        build_probe(hipcc)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, probe="--probe" in sys.argv))

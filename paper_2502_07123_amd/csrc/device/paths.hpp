@@ -289,8 +289,10 @@ __host__ __device__ __forceinline__ void fixed_step(XSide& s, int64_t z, int64_t
 // ------------------------------------------------------------- path kernel body
 // EST: MLMC_EST_*; ARITH: arithmetic of the table side (APPROX/CORR) or of the
 // plain side (PLAIN: FP64 or FP32); NP: 1 (payoff_single) or NPAY (payoff_mask);
-// TRACK: keep Asian sums and running minima; F: indices per word (1 = unpacked).
-template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
+// TRACK: keep Asian sums and running minima; F: indices per word (1 = unpacked);
+// X32: the correction estimator's exact side in FP32 (FP32 inverse normal and
+// FP32 Algorithm 1 arithmetic) instead of FP64.
+template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F, bool X32 = false>
 struct PathBody {
     static constexpr int WPB = 4 * F;                                  // normals per block
     static constexpr int WPB_TZ = 2 + (F % 2 ? 0 : (F % 4 ? 1 : (F % 8 ? 2 : 3)));   // trailing zeros
@@ -303,7 +305,9 @@ struct PathBody {
     // the float low-precision side's type (FP16 or FP32)
     using AT = typename std::conditional<HALF, _Float16, float>::type;
     static constexpr int TAB_BYTES = !HAS_TABLE ? 0 : (HALF ? 4 : 8);
-    using ExactT = typename std::conditional<PLAIN32, float, double>::type;
+    // the exact side in FP32: the plain-FP32 estimator, or a correction with X32
+    static constexpr bool EXACT32 = PLAIN32 || (EST == MLMC_EST_CORR && X32);
+    using ExactT = typename std::conditional<EXACT32, float, double>::type;
 
     // tab: table of 2^q entries (LDS on the device, host memory in checks)
     __host__ __device__ __forceinline__ static void run_group(const LevelDev& L, const WorkDev& W,
@@ -393,7 +397,7 @@ struct PathBody {
         if (HAS_TABLE) k = index_field(J, fi, q);
         if (n == 0) { first_word = J; first_index = k; }
         if (HAS_EXACT) {
-            if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J), L, coarse_on, odd, TRACK);
+            if (EXACT32) exact_step<MIL>(ex, norminv_f32(coupled_word(L, tab, J)), L, coarse_on, odd, TRACK);
             else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J)), L, coarse_on, odd, TRACK);
         }
         if (HAS_TABLE) {
@@ -809,13 +813,13 @@ struct PathBody {
     __host__ __device__ __forceinline__ static void exact_pair(const LevelDev& L, const void* tab, uint32_t J0,
                                                                uint32_t J1, FSide<ExactT>& ex, FSide<AT>& ap) {
         const int sh = 32 - L.q;
-        if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J0), L, true, false, TRACK);
+        if (EXACT32) exact_step<MIL>(ex, norminv_f32(coupled_word(L, tab, J0)), L, true, false, TRACK);
         else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J0)), L, true, false, TRACK);
         if (HAS_TABLE) {
             const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[J0 >> sh];
             table_step<MIL, AT>(ap, e.z, e.s, L, true, false, TRACK);
         }
-        if (PLAIN32) exact_step<MIL>(ex, norminv_f32(J1), L, true, true, TRACK);
+        if (EXACT32) exact_step<MIL>(ex, norminv_f32(coupled_word(L, tab, J1)), L, true, true, TRACK);
         else exact_step<MIL>(ex, norminv_f64(coupled_word(L, tab, J1)), L, true, true, TRACK);
         if (HAS_TABLE) {
             const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[J1 >> sh];
@@ -929,20 +933,17 @@ struct PathBody {
         const u32x4 r = philox_group_keys(W, g);
         const uint32_t wd[4] = {r.x, r.y, r.z, r.w};
         const uint64_t path0 = g * 4u;
-        const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
-        const ExactT eb = PLAIN32 ? ExactT(L.fb) : ExactT(L.b);
+        const ExactT ek = EXACT32 ? ExactT(L.fk) : ExactT(L.k);
+        const ExactT eb = EXACT32 ? ExactT(L.fb) : ExactT(L.b);
         const int sh = 32 - L.q;
         // the four inverse normals together (norminv_*_x4: interleaved chains, the
         // rare tails after), the same values as one at a time
         ExactT Z[4];
-        if constexpr (PLAIN32) {
-            norminv_f32_x4(wd, Z);
-        } else {
-            uint32_t Je[4];
+        uint32_t Je[4];
 #pragma unroll
-            for (int wi = 0; wi < 4; ++wi) Je[wi] = coupled_word(L, tab, wd[wi]);
-            norminv_f64_x4(Je, Z);
-        }
+        for (int wi = 0; wi < 4; ++wi) Je[wi] = coupled_word(L, tab, wd[wi]);
+        if constexpr (EXACT32) norminv_f32_x4(Je, Z);
+        else norminv_f64_x4(Je, Z);
 #pragma unroll
         for (int wi = 0; wi < 4; ++wi) {
             const uint32_t J = wd[wi];
@@ -980,8 +981,8 @@ struct PathBody {
         const int lev = L.level;
         MLMC_GLOBAL mlmc_path_record* rec =
             W.debug ? global_ptr<mlmc_path_record>(W.debug) + (pidx - W.path_begin) : nullptr;
-        const ExactT ek = PLAIN32 ? ExactT(L.fk) : ExactT(L.k);
-        const ExactT eb = PLAIN32 ? ExactT(L.fb) : ExactT(L.b);
+        const ExactT ek = EXACT32 ? ExactT(L.fk) : ExactT(L.k);
+        const ExactT eb = EXACT32 ? ExactT(L.fb) : ExactT(L.b);
 #pragma unroll
         for (int slot = 0; slot < NP; ++slot) {
             const int p = NP == 1 ? L.payoff_single : slot;

@@ -336,6 +336,12 @@ mlmc_status validate_precision(const mlmc_precision* prec, int estimator, const 
                                std::string& err) {
     if (!prec) { err = "precision is NULL"; return MLMC_E_INVALID; }
     if (prec->struct_size != sizeof(mlmc_precision)) { err = "mlmc_precision.struct_size mismatch"; return MLMC_E_VERSION; }
+    if (prec->exact_side != 0 && prec->exact_side != 1) { err = "exact_side must be 0 (FP64) or 1 (FP32)"; return MLMC_E_INVALID; }
+    if (estimator == MLMC_EST_CORR && prec->exact_side == 1 && prec->arith != MLMC_ARITH_FP32 &&
+        prec->arith != MLMC_ARITH_FP16) {
+        err = "an FP32 exact side needs an FP32 or FP16 table side";
+        return MLMC_E_INVALID;
+    }
     if (estimator == MLMC_EST_PLAIN) {
         if (prec->arith != MLMC_ARITH_FP64 && prec->arith != MLMC_ARITH_FP32) { err = "PLAIN supports FP64 and FP32"; return MLMC_E_INVALID; }
         if (prec->packed) { err = "packed indices apply to APPROX only"; return MLMC_E_INVALID; }
@@ -488,6 +494,7 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
     v.np = popcount32(p->payoff_mask) == 1 ? 1 : NPAY;
     v.track = ((p->payoff_mask >> MLMC_PAY_ASIAN) & 1u) || ((p->payoff_mask >> MLMC_PAY_BARRIER) & 1u);
     v.fields = (estimator == MLMC_EST_APPROX && prec->packed) ? 32 / prec->table_bits : 1;
+    v.exact32 = estimator == MLMC_EST_CORR && prec->exact_side == 1;
     out.table.clear();
     if (estimator == MLMC_EST_PLAIN) return MLMC_OK;
 

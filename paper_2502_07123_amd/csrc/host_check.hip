@@ -20,7 +20,7 @@ struct HostGroups {
     SlotDev out{};
     template <class Tag>
     void operator()(Tag) {
-        using B = PathBody<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields>;
+        using B = PathBody<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields, Tag::x32>;
         const uint64_t N = uint64_t(1) << L->level;
         const uint64_t S = group_span(L->level, B::WPB);
         const uint64_t G = S >> L->level;

@@ -54,7 +54,9 @@ struct RedLds {
 
 // Block sum of the per-thread accumulators (butterfly in each wave, then the waves
 // in index order) written by thread 0 to *out; the counts come as 64-bit values.
-template <int NP, bool CORR, bool INTS>
+// FULL: the whole SlotDev (zeros in the fields the variant does not fill: a work's
+// result); else only the fields the reduction reads (a tile's partial sums).
+template <int NP, bool CORR, bool INTS, bool FULL>
 __device__ __forceinline__ void block_store_counts(Acc<NP>& a, uint64_t cn, uint64_t csat, uint64_t cnf,
                                                    SlotDev* out, RedLds& r) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -113,13 +115,34 @@ __device__ __forceinline__ void block_store_counts(Acc<NP>& a, uint64_t cn, uint
             s.sat += r.c[w][1];
             s.nonfinite += r.c[w][2];
         }
-        *out = s;
+        if (FULL) {
+            *out = s;
+        } else {
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                out->s1[p] = s.s1[p];
+                out->s2[p] = s.s2[p];
+                if (CORR) {
+                    out->e1[p] = s.e1[p];
+                    out->e2[p] = s.e2[p];
+                }
+                if (INTS) {
+                    out->i1[p] = s.i1[p];
+                    out->i2lo[p] = s.i2lo[p];
+                    out->i2hi[p] = s.i2hi[p];
+                }
+            }
+            out->n = s.n;
+            out->sat = s.sat;
+            out->nonfinite = s.nonfinite;
+        }
     }
 }
 
+// a tile's partial sums
 template <int NP, bool CORR, bool INTS>
 __device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r) {
-    block_store_counts<NP, CORR, INTS>(a, a.n, a.sat, a.nonfinite, out, r);
+    block_store_counts<NP, CORR, INTS, false>(a, a.n, a.sat, a.nonfinite, out, r);
 }
 
 // Exact-normal kernels carry the FP64 inverse normal's constants, fixed-point kernels
@@ -131,12 +154,12 @@ constexpr int max_threads() {
     return EST == MLMC_EST_APPROX && ARITH != MLMC_ARITH_FIXED && NP == 1 ? 1024 : 256;
 }
 
-template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
+template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F, bool X32>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, max_threads<EST, ARITH, NP>())))
 k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles,
         const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
         const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
-    using Body = PathBody<EST, ARITH, MIL, NP, TRACK, F>;
+    using Body = PathBody<EST, ARITH, MIL, NP, TRACK, F, X32>;
     constexpr bool CORR = EST == MLMC_EST_CORR;
     constexpr bool INTS = ARITH == MLMC_ARITH_FIXED && EST == MLMC_EST_APPROX;
     extern __shared__ __align__(16) uint8_t s_tab[];
@@ -164,13 +187,6 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
                     if (!Body::ysample(L, s_tab, k, yt)) s_ybad = 1u;
                 __syncthreads();
                 ytab = s_ybad == 0u;
-            } else if (Body::EX0 && L.level == 0 && uint32_t(NP) * L.table_entries <= YTAB_MAX_ENTRIES) {
-                // the correction estimator's per-index approximate-side samples
-                double* yt = reinterpret_cast<double*>(s_tab + L.table_bytes);
-                for (uint32_t k = threadIdx.x; k < L.table_entries; k += blockDim.x)
-                    Body::ya_sample(L, s_tab, k, yt);
-                __syncthreads();
-                ytab = true;
             }
         }
         Acc<NP> acc;
@@ -194,11 +210,6 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
                 const uint32_t c = hist[k];
                 if (c) Body::hist_accumulate(L, s_tab, k, c, acc);
             }
-        } else if (Body::EX0 && L.level == 0 && !W.debug && (!Body::HAS_TABLE || ytab)) {
-            // level 0 of the exact-normal estimators: a group is one Philox block
-            const double* yt = reinterpret_cast<const double*>(s_tab + L.table_bytes);
-            for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
-                Body::exact0_group(L, W, g, s_tab, yt, acc);
         } else if (Body::HAS_EXACT && W.zbuf) {
             // normals computed ahead: a group is one path
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
@@ -212,6 +223,49 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles
                 Body::run_group(L, W, g, s_tab, acc);
         }
         block_store<NP, CORR, INTS>(acc, &slots[td.slot], red);
+    }
+}
+
+// Level 0 of the exact-normal estimators (plain; correction with a float table
+// side) in a kernel of its own, so that its registers are allocated for this loop
+// alone: a level-0 path is one step, four paths per Philox block
+// (PathBody::exact0_group, the four inverse normals interleaved).  The correction
+// estimator's approximate-side sample is a function of the table index, tabulated
+// per level in LDS (ya_sample) after the step table.  Same per-path operations,
+// tiles and block reduction as k_paths, so the sums are the same bit for bit.
+template <int EST, int ARITH, bool MIL, int NP, bool TRACK, bool X32>
+__global__ void __launch_bounds__(256)
+k_exact0(const WorkTilesDev* __restrict__ wtiles, uint32_t n_wt, uint32_t n_tiles,
+         const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
+         const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
+    using Body = PathBody<EST, ARITH, MIL, NP, TRACK, 1, X32>;
+    static_assert(Body::EX0, "level-0 kernel of an exact-normal estimator");
+    constexpr bool CORR = EST == MLMC_EST_CORR;
+    extern __shared__ __align__(16) uint8_t s_tab[];
+    __shared__ RedLds red;
+    uint32_t cur = 0xFFFFFFFFu;
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const TileDev td = tile_of(wtiles, n_wt, t);
+        const WorkDev W = works[td.work];
+        const LevelDev& L = levels[W.lvl];
+        if (Body::HAS_TABLE && W.lvl != cur) {
+            __syncthreads();
+            const uint4* src = reinterpret_cast<const uint4*>(tables + L.table_off);
+            uint4* dst = reinterpret_cast<uint4*>(s_tab);
+            for (uint32_t i = threadIdx.x; i < (L.table_bytes >> 4); i += blockDim.x) dst[i] = src[i];
+            __syncthreads();
+            double* yt = reinterpret_cast<double*>(s_tab + L.table_bytes);
+            for (uint32_t k = threadIdx.x; k < L.table_entries; k += blockDim.x) Body::ya_sample(L, s_tab, k, yt);
+            __syncthreads();
+            cur = W.lvl;
+        }
+        Acc<NP> acc;
+        acc_zero(acc);
+        const double* yt = reinterpret_cast<const double*>(s_tab + L.table_bytes);
+        const uint64_t gend = td.group_begin + td.n_groups;
+        for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
+            Body::exact0_group(L, W, g, s_tab, yt, acc);
+        block_store<NP, CORR, false>(acc, &slots[td.slot], red);
     }
 }
 
@@ -302,7 +356,7 @@ __device__ __forceinline__ void reduce_work(const SlotDev* __restrict__ sl, uint
         sat += x.sat;
         nf += x.nonfinite;
     }
-    block_store_counts<NP, CORR, INTS>(a, n, sat, nf, dst, r);
+    block_store_counts<NP, CORR, INTS, true>(a, n, sat, nf, dst, r);
 }
 
 __global__ void __launch_bounds__(REDUCE_THREADS)
@@ -339,21 +393,37 @@ using PathKernel = void (*)(const WorkTilesDev*, uint32_t, uint32_t, const WorkD
 
 namespace {
 struct InfoOf {
+    bool l0 = false;
     VariantInfo out{nullptr, 0, 0, 0};
     template <class Tag>
     void operator()(Tag) {
-        using B = PathBody<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields>;
-        out = VariantInfo{reinterpret_cast<void*>(
-                              &k_paths<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields>),
-                          B::WPB, B::TAB_BYTES, max_threads<Tag::est, Tag::arith, Tag::np>()};
+        using B = PathBody<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::fields, Tag::x32>;
+        if (!l0) {
+            out = VariantInfo{reinterpret_cast<void*>(&k_paths<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track,
+                                                               Tag::fields, Tag::x32>),
+                              B::WPB, B::TAB_BYTES, max_threads<Tag::est, Tag::arith, Tag::np>()};
+            return;
+        }
+        if constexpr (B::EX0) {
+            out = VariantInfo{reinterpret_cast<void*>(
+                                  &k_exact0<Tag::est, Tag::arith, Tag::mil, Tag::np, Tag::track, Tag::x32>),
+                              B::WPB, B::TAB_BYTES, 256};
+        }
     }
 };
 }  // namespace
 
 VariantInfo variant_info(const Variant& v) {
     InfoOf f;
+    f.l0 = v.l0;
     if (!dispatch_variant(v, f)) return VariantInfo{nullptr, 0, 0, 0};
     return f.out;
+}
+
+bool has_level0_kernel(const Variant& v) {
+    Variant w = v;
+    w.l0 = true;
+    return variant_info(w).fn != nullptr;
 }
 
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,

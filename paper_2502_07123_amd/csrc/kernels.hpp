@@ -15,26 +15,28 @@ struct Variant {
     int est, arith, scheme, np;
     bool track;
     int fields;
+    bool l0 = false;    // level-0 works of an exact-normal estimator in their own kernel
+    bool exact32 = false;   // correction estimator with an FP32 exact side
 };
 
-template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F>
+template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F, bool X32 = false>
 struct VTag {
     static constexpr int est = EST, arith = ARITH, np = NP, fields = F;
-    static constexpr bool mil = MIL, track = TRACK;
+    static constexpr bool mil = MIL, track = TRACK, x32 = X32;
 };
 
 namespace detail {
-template <int EST, int ARITH, bool MIL, int F, class Fn>
+template <int EST, int ARITH, bool MIL, int F, bool X32, class Fn>
 bool pick_np(const Variant& v, Fn& fn) {
-    if (v.np != 1) { fn(VTag<EST, ARITH, MIL, NPAY, true, F>{}); return true; }
-    if (v.track) { fn(VTag<EST, ARITH, MIL, 1, true, F>{}); return true; }
-    fn(VTag<EST, ARITH, MIL, 1, false, F>{});
+    if (v.np != 1) { fn(VTag<EST, ARITH, MIL, NPAY, true, F, X32>{}); return true; }
+    if (v.track) { fn(VTag<EST, ARITH, MIL, 1, true, F, X32>{}); return true; }
+    fn(VTag<EST, ARITH, MIL, 1, false, F, X32>{});
     return true;
 }
-template <int EST, int ARITH, int F, class Fn>
+template <int EST, int ARITH, int F, class Fn, bool X32 = false>
 bool pick_mil(const Variant& v, Fn& fn) {
-    return v.scheme == MLMC_MILSTEIN ? pick_np<EST, ARITH, true, F>(v, fn)
-                                     : pick_np<EST, ARITH, false, F>(v, fn);
+    return v.scheme == MLMC_MILSTEIN ? pick_np<EST, ARITH, true, F, X32>(v, fn)
+                                     : pick_np<EST, ARITH, false, F, X32>(v, fn);
 }
 }  // namespace detail
 
@@ -66,6 +68,12 @@ bool dispatch_variant(const Variant& v, Fn& fn) {
             }
         case MLMC_EST_CORR:
             if (v.fields != 1) return false;
+            if (v.exact32) {
+                // FP32 exact side (float table sides only)
+                if (v.arith == MLMC_ARITH_FP32) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP32, 1, Fn, true>(v, fn);
+                if (v.arith == MLMC_ARITH_FP16) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP16, 1, Fn, true>(v, fn);
+                return false;
+            }
             if (v.arith == MLMC_ARITH_FIXED) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FIXED, 1>(v, fn);
             if (v.arith == MLMC_ARITH_FP32) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP32, 1>(v, fn);
             if (v.arith == MLMC_ARITH_FP16) return pick_mil<MLMC_EST_CORR, MLMC_ARITH_FP16, 1>(v, fn);
@@ -83,6 +91,10 @@ struct VariantInfo {
 };
 
 VariantInfo variant_info(const Variant& v);   // fn == nullptr when not compiled
+
+// Whether level-0 works of variant v (no debug records, level 0, table of at most
+// YTAB_MAX_ENTRIES payoff slots x entries) run in the level-0 kernel.
+bool has_level0_kernel(const Variant& v);
 
 // n_tiles tiles generated from n_wt work descriptors (tile_of)
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,

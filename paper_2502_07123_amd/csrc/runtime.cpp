@@ -59,8 +59,8 @@ void slot_to_sums(const SlotDev& s, int i, mlmc_sums& o) {
 }
 
 namespace {
-using VKey = std::tuple<int, int, int, int, bool, int>;
-VKey vkey(const Variant& v) { return VKey{v.est, v.arith, v.scheme, v.np, v.track, v.fields}; }
+using VKey = std::tuple<int, int, int, int, bool, int, bool, bool>;
+VKey vkey(const Variant& v) { return VKey{v.est, v.arith, v.scheme, v.np, v.track, v.fields, v.l0, v.exact32}; }
 
 struct LaunchGroup {
     Variant v;
@@ -112,7 +112,8 @@ void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
     mlmc_kernel_stat* st = nullptr;
     for (auto& x : ctx->stats)
         if (x.estimator == v.est && x.arith == v.arith && x.scheme == v.scheme && x.fields == v.fields &&
-            x.payoffs == v.np && x.track == int(v.track))
+            x.payoffs == v.np && x.track == int(v.track) && x.level0 == int(v.l0) &&
+            x.exact32 == int(v.exact32))
             st = &x;
     if (!st) {
         mlmc_kernel_stat z;
@@ -123,6 +124,8 @@ void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
         z.fields = v.fields;
         z.payoffs = v.np;
         z.track = v.track ? 1 : 0;
+        z.level0 = v.l0 ? 1 : 0;
+        z.exact32 = v.exact32 ? 1 : 0;
         ctx->stats.push_back(z);
         st = &ctx->stats.back();
     }
@@ -131,6 +134,12 @@ void add_stat(mlmc_context* ctx, const Variant& v, float ms, uint64_t steps) {
     st->path_steps += steps;
 }
 }  // namespace
+
+bool level0_kernel_for(const Variant& v, int level, bool debug, const LevelDev& L) {
+    if (level != 0 || debug || v.est == MLMC_EST_APPROX) return false;
+    if (v.est == MLMC_EST_CORR && uint32_t(v.np) * L.table_entries > YTAB_MAX_ENTRIES) return false;
+    return has_level0_kernel(v);
+}
 
 uint32_t block_for(const Tuning& t, const Variant& v, const VariantInfo& vi) {
     return std::min<uint32_t>(vi.tab_bytes && v.est == MLMC_EST_APPROX ? t.block_table : t.block_exact,
@@ -297,7 +306,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     // 2. variants -> tiles (a work's tiles are contiguous; slot = tile index)
     std::map<VKey, LaunchGroup> groups;
     for (size_t i = 0; i < works.size(); ++i) {
-        const Variant& v = lvl_var[wdev[i].lvl];
+        Variant v = lvl_var[wdev[i].lvl];
+        v.l0 = level0_kernel_for(v, works[i].level, works[i].debug != 0, levels[wdev[i].lvl]);
         auto& g = groups[vkey(v)];
         g.v = v;
         g.works.push_back(static_cast<uint32_t>(i));
@@ -330,7 +340,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
                             (w.n << w.level) <= ctx->tune.zb_max_positions &&
                             (w.n << w.level) * 12 <= ctx->ws_bytes / 4;
             if (zb) {
-                const bool f32 = w.est == MLMC_EST_PLAIN && w.prec->arith == MLMC_ARITH_FP32;
+                const bool f32 = (w.est == MLMC_EST_PLAIN && w.prec->arith == MLMC_ARITH_FP32) ||
+                                 lvl_var[wdev[wi].lvl].exact32;
                 zb_f32[wi] = f32 ? 1 : 0;
                 const uint64_t pos = w.n << w.level;
                 zb_bytes[wi] = align_up(pos * 4, 256) + align_up(pos * (f32 ? 4 : 8), 256);
@@ -715,6 +726,8 @@ void option_result(const OptionRun& o, mlmc_result& r) {
             if (s.n) {
                 est += s_mean(s);
                 var += s_var(s) / static_cast<double>(s.n);
+                if (e == MLMC_EST_CORR) r.exact_sides |= o.cfg.prec[l].exact_side == 1 ? 2 : 1;
+                if (e == MLMC_EST_PLAIN) r.exact_sides |= 4;
             }
         }
     r.estimate = sc * est;

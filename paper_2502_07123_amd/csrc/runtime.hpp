@@ -42,6 +42,11 @@ struct Tuning {
 // The calling thread's last error message of mlmc_level_sums_static ("" if none).
 const char* static_last_error();
 
+// Whether a work of variant v at `level` runs in the level-0 kernel of the
+// exact-normal estimators (level 0, no debug records, the correction estimator's
+// per-index approximate samples fit in LDS).
+bool level0_kernel_for(const Variant& v, int level, bool debug, const LevelDev& L);
+
 // Threads per block of a kernel variant under a geometry.
 uint32_t block_for(const Tuning& t, const Variant& v, const VariantInfo& vi);
 

@@ -332,3 +332,27 @@ def test_two_stream_flights_equal_one_stream(how):
         assert runs[0] == runs[1]
     finally:
         c.close()
+
+
+def test_estimate_states_its_exact_side(ctx):
+    """The correction's exact side (reading R21): FP64 by default, FP32 on request;
+    the result says which, and both estimates agree with the closed form within
+    their error (the FP32 side changes the correction's samples by ~1e-7)."""
+    from math import erf, exp, log, sqrt
+    N = lambda x: 0.5 * (1.0 + erf(x / sqrt(2.0)))
+    d1 = (log(EURO["S0"] / EURO["K"]) + (EURO["r"] + 0.5 * EURO["sigma"] ** 2) * EURO["T"]) / (
+        EURO["sigma"] * sqrt(EURO["T"]))
+    bs = EURO["S0"] * N(d1) - EURO["K"] * exp(-EURO["r"] * EURO["T"]) * N(d1 - EURO["sigma"] * sqrt(EURO["T"]))
+    prob = M.make_problem("milstein", ("euro",), **EURO)
+    out = {}
+    for exact, bit in (("fp64", 1), ("fp32", 2)):
+        prec = M.make_precision("fp32", 8, exact=exact)
+        cfg = M.make_run_config(0.002, nested=True, prec=prec, theta=0.5, L_min=2, L_max=8, n_pilot=5000)
+        r = ctx.estimate(prob, cfg, SEED, option=1)
+        assert r["status"] == 0 and r["exact_sides"] & 3 == bit
+        out[exact] = r
+        assert abs(r["estimate"] - bs) < 4 * 0.002 * EURO["S0"], (exact, r["estimate"], bs)
+    # same uniforms: the two runs' level-0 correction means differ only by FP32 rounding
+    m64 = out["fp64"]["levels"][0]["mean"][M.EST_CORR]
+    m32 = out["fp32"]["levels"][0]["mean"][M.EST_CORR]
+    assert abs(m64 - m32) < 1e-5

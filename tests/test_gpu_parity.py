@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import paper_2502_07123_amd as M
-from parity import (CASES, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q, check_records,
+from parity import (CASES, GBM, METHOD_CASES, PAYS, SEED, WIDE_FMT, case_q, check_records, library_precision,
                     oracle_run)
 
 pytestmark = pytest.mark.gpu
@@ -30,7 +30,7 @@ def test_paths_and_sums(ctx, case, level, payoffs):
     scheme, est, arith, packed = case
     n, off = _n_for(level), 1000 + level
     prob = M.make_problem(scheme, payoffs, **GBM)
-    prec = M.make_precision(arith, case_q(case), packed, WIDE_FMT)
+    prec = library_precision(M, case)
     sums, rec = ctx.level_sums(prob, level, n, off, prec, est, SEED, debug=True)
     o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), payoffs)
     check_records(case, level, n, off, payoffs, sums, rec, o)
@@ -51,7 +51,7 @@ def test_exact_normals_ahead_and_inline(ctx, case, level, ahead):
     try:
         n, off = 3001, 77
         prob = M.make_problem(scheme, PAYS, **GBM)
-        prec = M.make_precision(arith, case_q(case), packed, WIDE_FMT)
+        prec = library_precision(M, case)
         sums, rec = ctx.level_sums(prob, level, n, off, prec, est, SEED, debug=True)
         o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS)
         check_records(case, level, n, off, PAYS, sums, rec, o)
@@ -69,7 +69,7 @@ def test_methods_2_3(ctx, mcase, level):
     scheme, est, arith, packed = case
     n, off = _n_for(level), 500 + level
     prob = M.make_problem(scheme, PAYS, **GBM)
-    prec = M.make_precision(arith, q, packed, WIDE_FMT, method=method)
+    prec = library_precision(M, case, q=q, method=method)
     sums, rec = ctx.level_sums(prob, level, n, off, prec, est, SEED, debug=True)
     o = oracle_run(case, level, np.arange(off, off + n, dtype=np.uint64), PAYS, method=method, q=q)
     check_records(case, level, n, off, PAYS, sums, rec, o, q=q)
