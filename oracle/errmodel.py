@@ -422,3 +422,72 @@ def kernel_formats(m: Model, d, scheme):
         prod("mul2", "X", s)
         add("X", "X", "mul2")
     return {v: (w, f) for v, (w, f) in F.items()}
+
+
+# ------------------------------------------- the level's low-precision side (Section 6)
+# Section 6 chooses, per level, the low-precision side that minimises the level
+# objective sqrt(V~ C~) + sqrt(V^D C^D).  Here the candidates are the GPU's table
+# sides and the cost of Section 5 is counted in issue cycles of the instruction
+# classes the path kernels use (instructions per fine path-step over issue rates in
+# wave-instructions per CU per clock) rather than in FPGA bit operations.
+GPU_RATES = {"f32": 1.447, "i32": 1.470, "f64_fma": 0.794, "f64_add": 0.871, "u64_mad": 0.831,
+             "lds_b64": 0.250, "lds_b32": 0.500}
+
+SIDE_CANDIDATES = (("fp32", 8, True), ("fp32", 6, True), ("fp32", 4, True), ("fp32", 10, False),
+                   ("fp32", 12, False), ("fp16", 8, True), ("fp16", 7, True), ("fp16", 10, False),
+                   ("fixed", 8, False), ("fixed", 10, False), ("fixed", 12, False))
+
+
+def side_instructions(arith, fields, scheme, level, estimator):
+    """Instructions per fine path-step by class of one sample of the approximate
+    (estimator 1) or correction (2) estimator with this table side."""
+    mil = scheme == "milstein"
+    n = {k: 0.0 for k in GPU_RATES}
+    word_share = 1.0 / fields if estimator == 1 else 1.0
+    n["u64_mad"] += 5 * word_share          # Philox4x32-10: 20 widening multiplies per 4 words
+    n["i32"] += 7.5 * word_share             # and 30 xors / adds
+    n["i32"] += 2.0 if (estimator == 1 and fields > 1) else 1.0     # table index
+    half = 0.5 if level >= 1 else 0.0        # a coarse step per two fine steps
+    if arith == "fixed":
+        n["u64_mad"] += 1 + half * (4 if mil else 2)
+        n["i32"] += 17 + half * (69 if mil else 35)
+        n["lds_b64"] += 1
+    else:
+        n["f32"] += 2 + half * (9 if mil else 5)
+        n["lds_b32" if arith == "fp16" else "lds_b64"] += 1
+    if estimator == 2:
+        n["f64_fma"] += 55 + (5 if mil else 2) + half * (9 if mil else 5)
+        n["f64_add"] += 5 + 8.0 / 2 ** level
+    else:
+        n["f64_add"] += 4.0 / 2 ** level
+    return n
+
+
+def side_cost(arith, q, packed, scheme, level, estimator, rates=GPU_RATES):
+    n = side_instructions(arith, 32 // q if packed else 1, scheme, level, estimator)
+    return sum(n[k] / rates[k] for k in n)
+
+
+def choose_side(m: Model, scheme, level, rates=GPU_RATES, fixed_d=None):
+    """The candidate side with the least level objective (first in order on ties):
+    V~ = V_level, V^D = v_indep(d) + S_Z MSE_q with d the significand bits (FP32 24,
+    FP16 11) or the fixed widths fixed_d, C = 2^l side_cost.  Returns
+    (arith, q, packed, objective, objective of FP32 q = 8 packed)."""
+    best = None
+    ref = None
+    for arith, q, packed in SIDE_CANDIDATES:
+        if arith == "fixed":
+            if fixed_d is None:
+                continue
+            d = np.asarray(fixed_d, dtype=np.float64)
+        else:
+            d = np.full(len(VARS), 24.0 if arith == "fp32" else 11.0)
+        vD = v_indep(m, d) + m.S[IX["Z"]] * float(normal.table_mse(q))
+        cA = 2 ** level * side_cost(arith, q, packed, scheme, level, 1, rates)
+        cC = 2 ** level * side_cost(arith, q, packed, scheme, level, 2, rates)
+        obj = math.sqrt(m.V_level * cA) + math.sqrt(vD * cC)
+        if ref is None:
+            ref = obj
+        if best is None or obj < best[3]:
+            best = (arith, q, packed, obj)
+    return best + (ref,)

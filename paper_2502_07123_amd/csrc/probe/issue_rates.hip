@@ -101,6 +101,39 @@ __global__ void __launch_bounds__(BLOCK) k_lds_b64(double* out, uint32_t seed) {
     out[blockIdx.x * BLOCK + threadIdx.x] = acc0 + acc1;
 }
 
+// random 4-byte reads of a 256-entry table (an FP16 step table's (Z~, s) pairs)
+__global__ void __launch_bounds__(BLOCK) k_lds_b32(float* out, uint32_t seed) {
+    __shared__ float tab[256];
+    for (int i = threadIdx.x; i < 256; i += BLOCK) tab[i] = i * 1e-3f;
+    __syncthreads();
+    const uint32_t inc = (threadIdx.x * 2654435761u + seed) | 1u;
+    uint32_t s0 = inc * 3u, s1 = inc * 7u;
+    float acc0 = 0.0f, acc1 = 0.0f;
+    for (int i = 0; i < ITERS; ++i) {
+        s0 += inc;
+        s1 += inc;
+        acc0 += tab[s0 >> 24];
+        acc1 += tab[s1 >> 24];
+    }
+    out[blockIdx.x * BLOCK + threadIdx.x] = acc0 + acc1;
+}
+
+// eight independent FP16 multiply-add chains per thread (scalar _Float16)
+__global__ void __launch_bounds__(BLOCK) k_f16_fma(_Float16* out, float seed) {
+    _Float16 a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = _Float16(seed + threadIdx.x + j);
+    const _Float16 m = _Float16(0.999f), c = _Float16(1e-3f);
+    for (int i = 0; i < ITERS; ++i) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = a[j] * m + c;
+    }
+    _Float16 s = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += a[j];
+    out[blockIdx.x * BLOCK + threadIdx.x] = s;
+}
+
 struct Probe {
     const char* name;
     int insts_per_iter;     // instructions of the class per loop iteration and thread
@@ -123,7 +156,8 @@ int main() {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 1;
     const Probe probes[] = {{"f32_fma", 8, 0}, {"i32_xor_add", 16, 1}, {"f64_fma", 8, 2},
-                            {"f64_add", 8, 3}, {"u64_mad", 8, 4},   {"lds_b64_random", 2, 5}};
+                            {"f64_add", 8, 3}, {"u64_mad", 8, 4},   {"lds_b64_random", 2, 5},
+                            {"lds_b32_random", 2, 6}, {"f16_fma", 8, 7}};
     for (const Probe& p : probes) {
         float best = 1e30f;
         for (int rep = 0; rep < 5; ++rep) {
@@ -134,7 +168,9 @@ int main() {
                 case 2: hipLaunchKernelGGL(k_f64_fma, dim3(grid), dim3(BLOCK), 0, 0, (double*)buf, double(rep)); break;
                 case 3: hipLaunchKernelGGL(k_f64_add, dim3(grid), dim3(BLOCK), 0, 0, (double*)buf, double(rep)); break;
                 case 4: hipLaunchKernelGGL(k_u64_mad, dim3(grid), dim3(BLOCK), 0, 0, (uint32_t*)buf, uint32_t(rep)); break;
-                default: hipLaunchKernelGGL(k_lds_b64, dim3(grid), dim3(BLOCK), 0, 0, (double*)buf, uint32_t(rep)); break;
+                case 5: hipLaunchKernelGGL(k_lds_b64, dim3(grid), dim3(BLOCK), 0, 0, (double*)buf, uint32_t(rep)); break;
+                case 6: hipLaunchKernelGGL(k_lds_b32, dim3(grid), dim3(BLOCK), 0, 0, (float*)buf, uint32_t(rep)); break;
+                default: hipLaunchKernelGGL(k_f16_fma, dim3(grid), dim3(BLOCK), 0, 0, (_Float16*)buf, float(rep)); break;
             }
             (void)hipEventRecord(b);
             if (hipEventSynchronize(b) != hipSuccess) return 1;
