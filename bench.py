@@ -155,26 +155,62 @@ def level_mean(S, l, scale):
     return scale * float(s["sum1"][2 * l] / s["n"][2 * l] + s["sum1"][2 * l + 1] / s["n"][2 * l + 1])
 
 
-def cpu_baseline(Na, Nc, budget_paths_steps=1.5e8):
-    """The oracle on a bounded sample of the same works (same levels and estimators,
-    sample sizes proportional to N_l, M_l): single-threaded numpy."""
-    import numpy as np
+def _oracle_work(item):
+    """One chunk of the CPU baseline: (level, estimator, path offset, paths, packed)."""
     from oracle.mlmc import level_sums
     from oracle.paths import Precision, Problem
-    p = Problem("milstein", barrier=0.0, **GBM)
-    total = sum(int(Na[l]) << l for l in range(LEVELS)) + sum(int(Nc[l]) << l for l in range(LEVELS))
-    f = min(1.0, budget_paths_steps / total)
-    t0 = time.perf_counter()
-    steps = 0
+    l, est, off, n, packed = item
+    level_sums(Problem("milstein", barrier=0.0, **GBM), l, n, off, Precision("fp32", Q, packed), est, SEED, 0,
+               ("euro",))
+    return n << l
+
+
+def oracle_pool():
+    """Worker processes for the CPU baseline, forked before anything touches the GPU
+    (a process that has initialised the GPU forks no workers); one per core of this
+    process's affinity set, at most 16."""
+    import multiprocessing as mp
+    P = max(1, min(16, len(os.sched_getaffinity(0))))
+    return mp.get_context("fork").Pool(P), P
+
+
+def _sample_items(Na, Nc, f, parts):
+    items = []
     for l in range(LEVELS):
         for est, N, packed in ((1, Na[l], True), (2, Nc[l], False)):
             n = max(256, int(round(int(N) * f)))
-            level_sums(p, l, n, 0, Precision("fp32", Q, packed), est, SEED, 0, ("euro",))
-            steps += n << l
-    dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps:.3g} fine path-steps: the 18 (level, estimator) works with N_l, M_l "
-                      f"scaled by {f:.3g} (>= 256 paths each), single-threaded numpy"}
+            k = max(1, min(parts, n // 256))
+            for j in range(k):
+                a, b = n * j // k, n * (j + 1) // k
+                items.append((l, est, a, b - a, packed))
+    return items
+
+
+def cpu_baseline(Na, Nc, pool=None, P=1, budget_1core=6e7, budget_per_core=1.5e8):
+    """The oracle on a bounded sample of the same works (same levels and estimators,
+    sample sizes proportional to N_l, M_l), as it stands (numpy, vectorised across
+    paths): first on one core, then over P worker processes with disjoint path
+    ranges of a sample P times larger."""
+    total = sum(int(Na[l]) << l for l in range(LEVELS)) + sum(int(Nc[l]) << l for l in range(LEVELS))
+    f1 = min(1.0, budget_1core / total)
+    t0 = time.perf_counter()
+    steps1 = sum(_oracle_work(it) for it in _sample_items(Na, Nc, f1, 1))
+    one = steps1 / (time.perf_counter() - t0)
+    out = {"value": one, "unit": "path-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{steps1:.3g} fine path-steps: the 18 (level, estimator) works with N_l, M_l "
+                     f"scaled by {f1:.3g} (>= 256 paths each), numpy on one core",
+           "value_1core": one}
+    if pool is None or P <= 1:
+        return out
+    fP = min(1.0, budget_per_core * P / total)
+    items = _sample_items(Na, Nc, fP, 4 * P)
+    t0 = time.perf_counter()
+    stepsP = sum(pool.map(_oracle_work, items, chunksize=1))
+    out.update(value=stepsP / (time.perf_counter() - t0), cores=P,
+               sample=f"{stepsP:.3g} fine path-steps: the 18 (level, estimator) works with N_l, M_l scaled "
+                      f"by {fP:.3g} (>= 256 paths each), split into disjoint path ranges over {P} worker "
+                      f"processes (numpy); one core alone: {one:.3g} path-steps/s on {steps1:.3g}")
+    return out
 
 
 def main():
@@ -210,6 +246,7 @@ def main():
 
     if args.batch or args.serving or args.per_level:
         return main_workloads(args)
+    pool, P = (None, 1) if args.no_cpu else oracle_pool()
     import numpy as np
     import torch
     import paper_2502_07123_amd as M
@@ -259,6 +296,7 @@ def main():
     ests, top = [], []
 
     host = {"enqueue_s": 0.0, "wait_s": 0.0}
+    done_at = []                       # completion times of the timed steps (D5)
 
     def run_steps(k_steps, record):
         nonlocal off
@@ -269,6 +307,7 @@ def main():
                 b.wait()
                 host["wait_s"] += time.perf_counter() - t1
                 if record:
+                    done_at.append(time.perf_counter())
                     ests.append(combine_np(b.sums, scale))
                     top.append(level_mean(b.sums, LEVELS - 1, scale))
             b.offsets[:] = off
@@ -281,6 +320,7 @@ def main():
             if b._pending is not None:
                 b.wait()
                 if record:
+                    done_at.append(time.perf_counter())
                     ests.append(combine_np(b.sums, scale))
                     top.append(level_mean(b.sums, LEVELS - 1, scale))
 
@@ -314,6 +354,11 @@ def main():
                            "path_steps_per_step": per_step_steps,
                            "alg_lane_ops_per_step": ops}}
 
+    # per-step times: intervals between consecutive step completions in the timed
+    # region (steps are pipelined, so these are the throughput intervals)
+    iv = np.diff(np.asarray([t0] + done_at)) * 1e3
+    step_ms = {"median": float(np.median(iv)), "p10": float(np.percentile(iv, 10)),
+               "p90": float(np.percentile(iv, 90)), "steps": int(iv.size)}
     bs = closed_form(dict(GBM, kind="euro"))
     last = ests[-1][0]
     bias = -float(np.mean(top))
@@ -327,17 +372,22 @@ def main():
         # timed steps' level-L means; the step error less it is the sampling error
         "bias_estimate": bias, "step_error_less_bias": last - bs - bias,
         "N_approx": [int(x) for x in Na], "N_corr": [int(x) for x in Nc],
+        "ms_per_step_distribution": step_ms,
         "tuning": tuning,
         # host time per timed step in the library's enqueue (planning, copies, launches)
         # and in the wait for the step two back (the GPU still busy)
         "host_us_per_step": {k[:-2]: v * 1e6 / args.steps for k, v in host.items()},
         "kernels": [{"estimator": s["estimator"], "arith": s["arith"], "fields": s["fields"],
+                     "level0_kernel": s["level0"], "exact32": s["exact32"],
                      "launches": s["launches"], "ms": s["ms"],
                      "path_steps_per_s": s["path_steps"] / (s["ms"] * 1e-3)} for s in stats],
     }
     if not args.no_tte:
         extra["time_to_eps"] = time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale)
-    cpu = None if args.no_cpu else cpu_baseline(Na, Nc)
+    cpu = None if args.no_cpu else cpu_baseline(Na, Nc, pool, P)
+    if pool is not None:
+        pool.close()
+        pool.join()
     line = {
         "metric": "path-steps/s per level; time to RMSE eps, nested low-prec vs plain FP32",
         "value": value, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -353,12 +403,15 @@ def main():
     ctx.close()
 
 
-def calibrate(M, ctx, prob, prec_a, prec_c, level=4, n=1 << 22):
-    """ns per fine path-step of the approximate, correction and plain-FP32 kernels,
-    from one large launch each (after a warm-up launch)."""
+def calibrate(M, ctx, prob, prec_a, prec_c, level=4, n=1 << 22, exact32=False):
+    """ns per fine path-step of the approximate, correction and plain-FP32 kernels
+    (and, with exact32, of the correction with an FP32 exact side), from one large
+    launch each (after a warm-up launch)."""
     out = []
-    for est, prec in ((M.EST_APPROX, prec_a), (M.EST_CORR, prec_c),
-                      (M.EST_PLAIN, M.make_precision("fp32", Q))):
+    kinds = [(M.EST_APPROX, prec_a), (M.EST_CORR, prec_c), (M.EST_PLAIN, M.make_precision("fp32", Q))]
+    if exact32:
+        kinds.append((M.EST_CORR, M.make_precision("fp32", Q, exact="fp32")))
+    for est, prec in kinds:
         ctx.level_sums(prob, level, n, 0, prec, est, SEED + 99)
         ctx.set_timing(True)
         ctx.level_sums(prob, level, n, n, prec, est, SEED + 99)
@@ -395,40 +448,54 @@ def level_reference(M, ctx, prob, scale):
 
 
 def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale):
-    """Wall time of one on-line MLMC estimate to RMSE eps (price units), levels 0..8,
-    nested (FP32 table + FP64 correction) vs plain FP32 (exact FP32 normals); the
-    cost model uses the calibrated ns per path-step of each kernel class.  theta = 1
-    gives the whole budget to the sampling variance at the fixed finest level L
-    (variance eps^2), so the RMSE over TTE_SEEDS seeds is taken about E[P_L] (the
-    level-L reference); the error against Black-Scholes also holds the level-L bias."""
+    """Wall time of one on-line MLMC estimate to RMSE eps (price units), nested (FP32
+    table + FP64 correction; also with the correction's exact side in FP32) vs plain
+    FP32 (exact FP32 normals), each over TTE_SEEDS seeds, in two settings:
+      fixed:    levels 0..8, theta = 1 (the whole budget on the sampling variance at
+                the fixed finest level L), RMSE about E[P_L] (the level-L reference);
+      adaptive: theta = 1/2, L from 2 up to 10 by the bias test, RMSE about the
+                Black-Scholes price (bias and sampling error together).
+    Costs are the calibrated ns per path-step of each kernel class."""
     import numpy as np
     ref, ref_se = level_reference(M, ctx, prob, scale)
     bs = closed_form(dict(GBM, kind="euro"))
-    out = {"reference_level_L": ref, "reference_se": ref_se, "closed_form": bs, "seeds": TTE_SEEDS}
-    for name, nested in (("nested", True), ("plain_fp32", False)):
-        cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", theta=1.0, L_min=8, L_max=8,
-                                n_pilot=TTE_PILOT, costs=(c_p, c_a, c_c), plain_arith="fp32",
-                                prec=prec_a)
-        ctx.estimate(prob, cfg, SEED + 1)                  # warm (tables, caches)
-        ts, ests, steps = [], [], []
-        for rep in range(TTE_SEEDS):
-            t0 = time.perf_counter()
-            r = ctx.estimate(prob, cfg, SEED + 2 + rep)
-            ts.append(time.perf_counter() - t0)
-            ests.append(r["estimate"])
-            steps.append(r["path_steps"])
-        e = np.asarray(ests)
-        rmse = float(np.sqrt(np.mean((e - ref) ** 2)))
-        ci = [rmse * math.sqrt(TTE_SEEDS / CHI2_HI), rmse * math.sqrt(TTE_SEEDS / CHI2_LO)]
-        out[name] = {"seconds": float(np.median(ts)), "p10_s": float(np.percentile(ts, 10)),
-                     "p90_s": float(np.percentile(ts, 90)), "mean_estimate": float(e.mean()),
-                     "rmse": rmse, "rmse_ci95": ci, "rmse_within_eps": ci[0] <= EPS,
-                     "rmse_vs_closed_form": float(np.sqrt(np.mean((e - bs) ** 2))),
-                     "path_steps_median": float(np.median(steps))}
-    out["speedup"] = out["plain_fp32"]["seconds"] / out["nested"]["seconds"]
-    out["faster_at_equal_rmse"] = bool(out["nested"]["rmse_within_eps"] and out["plain_fp32"]["rmse_within_eps"]
-                                       and out["speedup"] > 1.0)
-    out["cost_ns_per_step"] = {"plain_fp32": c_p, "approx": c_a, "corr": c_c}
+    c_x = calibrate(M, ctx, prob, prec_a, M.make_precision("fp32", Q), exact32=True)[3]
+    prec_x = M.make_precision("fp32", Q, packed=True, exact="fp32")
+    out = {"reference_level_L": ref, "reference_se": ref_se, "closed_form": bs, "seeds": TTE_SEEDS,
+           "cost_ns_per_step": {"plain_fp32": c_p, "approx": c_a, "corr": c_c, "corr_exact_fp32": c_x}}
+    modes = (("nested", True, prec_a, c_c), ("nested_exact_fp32", True, prec_x, c_x),
+             ("plain_fp32", False, prec_a, c_c))
+    for setting, kw, truth in (("fixed", dict(theta=1.0, L_min=8, L_max=8), ref),
+                               ("adaptive", dict(theta=0.5, L_min=2, L_max=10), bs)):
+        res = {}
+        for name, nested, prec, cc in modes:
+            cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", n_pilot=TTE_PILOT,
+                                    costs=(c_p, c_a, cc), plain_arith="fp32", prec=prec, **kw)
+            ctx.estimate(prob, cfg, SEED + 1)                  # warm (tables, caches)
+            ts, ests, steps, Ls = [], [], [], []
+            for rep in range(TTE_SEEDS):
+                t0 = time.perf_counter()
+                r = ctx.estimate(prob, cfg, SEED + 2 + rep)
+                ts.append(time.perf_counter() - t0)
+                ests.append(r["estimate"])
+                steps.append(r["path_steps"])
+                Ls.append(r["L"])
+            e = np.asarray(ests)
+            rmse = float(np.sqrt(np.mean((e - truth) ** 2)))
+            ci = [rmse * math.sqrt(TTE_SEEDS / CHI2_HI), rmse * math.sqrt(TTE_SEEDS / CHI2_LO)]
+            res[name] = {"seconds": float(np.median(ts)), "p10_s": float(np.percentile(ts, 10)),
+                         "p90_s": float(np.percentile(ts, 90)), "mean_estimate": float(e.mean()),
+                         "rmse": rmse, "rmse_ci95": ci, "rmse_within_eps": ci[0] <= EPS,
+                         "rmse_vs_closed_form": float(np.sqrt(np.mean((e - bs) ** 2))),
+                         "L_median": float(np.median(Ls)), "path_steps_median": float(np.median(steps))}
+        for name in ("nested", "nested_exact_fp32"):
+            res[name]["speedup_vs_plain_fp32"] = res["plain_fp32"]["seconds"] / res[name]["seconds"]
+            res[name]["faster_at_equal_rmse"] = bool(res[name]["rmse_within_eps"] and
+                                                     res["plain_fp32"]["rmse_within_eps"] and
+                                                     res[name]["speedup_vs_plain_fp32"] > 1.0)
+        out[setting] = res
+    out["speedup"] = out["fixed"]["nested"]["speedup_vs_plain_fp32"]
+    out["faster_at_equal_rmse"] = out["fixed"]["nested"]["faster_at_equal_rmse"]
     return out
 
 
