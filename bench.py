@@ -226,6 +226,9 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="instead: the 256-option batched workload (nested vs plain FP32)")
     ap.add_argument("--batch-eps", default="1e-2,1e-3,1e-4")
+    ap.add_argument("--drivers", default="engine,host",
+                    help="sweep drivers of --batch / --serving: engine (device run states, graph "
+                         "replays) and/or host (sweeps planned on the host)")
     ap.add_argument("--serving", action="store_true",
                     help="instead: Poisson-arrival serving, p50/p99 latency (nested vs plain FP32)")
     ap.add_argument("--serve-rates", default="1000,5000,20000")
@@ -447,6 +450,23 @@ def level_reference(M, ctx, prob, scale):
     return closed_form(dict(GBM, kind="euro")) - scale * m, scale * math.sqrt(v)
 
 
+ARITH_NAMES = {1: "fp32", 2: "fp16", 3: "fixed"}
+
+
+def chosen_sides(M, ctx, prob, L_max=10, n_paths=1 << 16, q=8):
+    """Per-level table sides by Section 6's level objective with the measured
+    instruction-class costs (mlmc_choose_precision) from each level's error model
+    (sensitivities on the GPU over n_paths paths)."""
+    precs, info = [], []
+    for l in range(L_max + 1):
+        m = ctx.error_model(prob, l, n_paths, q, SEED + 555)
+        p, c = M.choose_precision(m)
+        precs.append(p)
+        info.append({"level": l, "arith": ARITH_NAMES[c["arith"]], "q": c["table_bits"], "packed": c["packed"],
+                     "objective_over_fp32_q8": c["objective"] / c["objective_fp32_q8"]})
+    return precs, info
+
+
 def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale):
     """Wall time of one on-line MLMC estimate to RMSE eps (price units), nested (FP32
     table + FP64 correction; also with the correction's exact side in FP32) vs plain
@@ -461,10 +481,12 @@ def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale):
     bs = closed_form(dict(GBM, kind="euro"))
     c_x = calibrate(M, ctx, prob, prec_a, M.make_precision("fp32", Q), exact32=True)[3]
     prec_x = M.make_precision("fp32", Q, packed=True, exact="fp32")
+    chosen, choices = chosen_sides(M, ctx, prob)
     out = {"reference_level_L": ref, "reference_se": ref_se, "closed_form": bs, "seeds": TTE_SEEDS,
-           "cost_ns_per_step": {"plain_fp32": c_p, "approx": c_a, "corr": c_c, "corr_exact_fp32": c_x}}
+           "cost_ns_per_step": {"plain_fp32": c_p, "approx": c_a, "corr": c_c, "corr_exact_fp32": c_x},
+           "chosen_sides": choices}
     modes = (("nested", True, prec_a, c_c), ("nested_exact_fp32", True, prec_x, c_x),
-             ("plain_fp32", False, prec_a, c_c))
+             ("nested_chosen", True, chosen, c_c), ("plain_fp32", False, prec_a, c_c))
     for setting, kw, truth in (("fixed", dict(theta=1.0, L_min=8, L_max=8), ref),
                                ("adaptive", dict(theta=0.5, L_min=2, L_max=10), bs)):
         res = {}
@@ -488,7 +510,7 @@ def time_to_eps(M, ctx, prob, prec_a, c_a, c_c, c_p, scale):
                          "rmse": rmse, "rmse_ci95": ci, "rmse_within_eps": ci[0] <= EPS,
                          "rmse_vs_closed_form": float(np.sqrt(np.mean((e - bs) ** 2))),
                          "L_median": float(np.median(Ls)), "path_steps_median": float(np.median(steps))}
-        for name in ("nested", "nested_exact_fp32"):
+        for name in ("nested", "nested_exact_fp32", "nested_chosen"):
             res[name]["speedup_vs_plain_fp32"] = res["plain_fp32"]["seconds"] / res[name]["seconds"]
             res[name]["faster_at_equal_rmse"] = bool(res[name]["rmse_within_eps"] and
                                                      res["plain_fp32"]["rmse_within_eps"] and
@@ -542,7 +564,7 @@ def _run_cfg(M, nested, eps, costs):
                              n_pilot=10_000, costs=costs, plain_arith="fp32", prec=prec)
 
 
-def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256):
+def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256, drivers=("engine",)):
     """Poisson arrivals (exponential gaps) of pricing requests at each rate: options
     as draw_options, eps = 10^U[-4,-2] (normalised), Milstein; nested (FP32 table +
     FP64 correction) or plain FP32.  Latency = arrival to result: the submission's
@@ -567,7 +589,8 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256)
         n = len(arr)
         opts = draw_options(o_rng, n)
         eps = 10.0 ** o_rng.uniform(-4, -2, n)
-        for mode in ("nested", "plain_fp32"):
+        for drv, mode in [(d, m) for d in drivers for m in ("nested", "plain_fp32")]:
+            ctx.set_driver(drv == "engine")
             nested = mode == "nested"
             reqs = (L.Request * n)()
             for i, o in enumerate(opts):
@@ -636,7 +659,8 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256)
                     cf_err.append((est[j] - v) / opts[j]["S0"] / eps[j])
             cf_err = np.asarray(cf_err)
             out.append({
-                "rate_per_s": rate, "mode": mode, "measured": int(meas.sum()), "completed": int(ok.sum()),
+                "rate_per_s": rate, "mode": mode, "driver": drv, "measured": int(meas.sum()),
+                "completed": int(ok.sum()),
                 "p50_ms": _pct(lat[ok] * 1e3, 50), "p99_ms": _pct(lat[ok] * 1e3, 99),
                 "mean_ms": float(np.mean(lat[ok]) * 1e3) if ok.any() else None,
                 "options_per_s": float(ok.sum() / span) if ok.any() else 0.0,
@@ -646,47 +670,52 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256)
                 "rms_err_over_eps": float(np.sqrt(np.mean(cf_err ** 2))) if cf_err.size else None,
                 "wall_s": wall,
                 "scheduler": {k: sst[k] for k in ("flights", "works", "plan_seconds", "land_seconds",
-                                                  "idle_seconds")},
+                                                  "idle_seconds", "engine", "slots", "bytes_per_request")},
             })
             print(json.dumps({"serving": out[-1]}), file=sys.stderr, flush=True)
     return out
 
 
-def batch(M, ctx, costs, eps_list, n_opt=256):
+def batch(M, ctx, costs, eps_list, n_opt=256, drivers=("engine",)):
     """The batched workload: n_opt options (draw_options with default_rng(1234)),
-    each to RMSE eps (normalised), all options' samples of a sweep in one launch
-    sequence; nested vs plain FP32.  Wall time of mlmc_estimate_batch."""
+    each to RMSE eps (normalised); nested vs plain FP32.  Wall time of
+    mlmc_estimate_batch, per sweep driver: 'engine' (run states on the device, one
+    graph replay per sweep of all options) or 'host' (each sweep planned on the host,
+    one launch sequence)."""
     import numpy as np
     rng = np.random.default_rng(1234)
     opts = draw_options(rng, n_opt)
     probs = [M.make_problem("milstein", (o["kind"],), S0=o["S0"], K=o["K"], r=o["r"], sigma=o["sigma"],
                             T=o["T"]) for o in opts]
     out = []
-    # one untimed call per mode first: the process-wide caches (table values, the
-    # kernels' first launches) are built once, not per request
-    first = {}
-    for mode in ("nested", "plain_fp32"):
-        t0 = time.perf_counter()
-        ctx.estimate_batch(probs, _run_cfg(M, mode == "nested", max(eps_list), costs), SEED + 99)
-        first[mode] = time.perf_counter() - t0
-    for eps in eps_list:
+    for drv in drivers:
+        ctx.set_driver(drv == "engine")
+        # one untimed call per mode first: the process-wide caches (table values, the
+        # kernels' first launches, the engine's graph) are built once, not per request
+        first = {}
         for mode in ("nested", "plain_fp32"):
-            cfg = _run_cfg(M, mode == "nested", eps, costs)
             t0 = time.perf_counter()
-            rs = ctx.estimate_batch(probs, cfg, SEED)
-            dt = time.perf_counter() - t0
-            errs = [(r["estimate"] - closed_form(o)) / o["S0"] / eps for r, o in zip(rs, opts)
-                    if closed_form(o) is not None]
-            ns = [sum(lv["n"][e] for lv in r["levels"] for e in range(3)) for r in rs]
-            out.append({"eps": eps, "mode": mode, "seconds": dt, "options": n_opt,
-                        "path_steps": int(sum(r["path_steps"] for r in rs)),
-                        "path_steps_per_s": sum(r["path_steps"] for r in rs) / dt,
-                        "sweeps_max": max(r["sweeps"] for r in rs), "L_max": max(r["L"] for r in rs),
-                        "samples_min": int(min(ns)), "samples_max": int(max(ns)),
-                        "closed_form_checked": len(errs),
-                        "rms_err_over_eps": float(np.sqrt(np.mean(np.square(errs)))),
-                        "first_call_seconds": first[mode]})
-            print(json.dumps({"batch": out[-1]}), file=sys.stderr, flush=True)
+            ctx.estimate_batch(probs, _run_cfg(M, mode == "nested", max(eps_list), costs), SEED + 99)
+            first[mode] = time.perf_counter() - t0
+        for eps in eps_list:
+            for mode in ("nested", "plain_fp32"):
+                cfg = _run_cfg(M, mode == "nested", eps, costs)
+                t0 = time.perf_counter()
+                rs = ctx.estimate_batch(probs, cfg, SEED)
+                dt = time.perf_counter() - t0
+                errs = [(r["estimate"] - closed_form(o)) / o["S0"] / eps for r, o in zip(rs, opts)
+                        if closed_form(o) is not None]
+                ns = [sum(lv["n"][e] for lv in r["levels"] for e in range(3)) for r in rs]
+                out.append({"eps": eps, "mode": mode, "driver": drv, "seconds": dt, "options": n_opt,
+                            "path_steps": int(sum(r["path_steps"] for r in rs)),
+                            "path_steps_per_s": sum(r["path_steps"] for r in rs) / dt,
+                            "sweeps_max": max(r["sweeps"] for r in rs), "L_max": max(r["L"] for r in rs),
+                            "samples_min": int(min(ns)), "samples_max": int(max(ns)),
+                            "closed_form_checked": len(errs),
+                            "rms_err_over_eps": float(np.sqrt(np.mean(np.square(errs)))),
+                            "first_call_seconds": first[mode]})
+                print(json.dumps({"batch": out[-1]}), file=sys.stderr, flush=True)
+    ctx.set_driver(True)
     return out
 
 
@@ -733,10 +762,12 @@ def main_workloads(args):
     costs = (c_p, c_a, c_c)
     line = {"cost_ns_per_step": {"plain_fp32": c_p, "approx": c_a, "corr": c_c}}
     if args.batch:
-        line["batch"] = batch(M, ctx, costs, [float(x) for x in args.batch_eps.split(",")])
+        line["batch"] = batch(M, ctx, costs, [float(x) for x in args.batch_eps.split(",")],
+                              drivers=tuple(args.drivers.split(",")))
     if args.serving:
         line["serving"] = serving(M, ctx, costs, [float(x) for x in args.serve_rates.split(",")],
-                                  args.serve_seconds)
+                                  args.serve_seconds, drivers=tuple(args.drivers.split(",")))
+        ctx.set_driver(True)
     if args.per_level:
         line["per_level_path_steps_per_s"] = per_level(M, ctx)
     torch.cuda.synchronize()

@@ -386,6 +386,20 @@ typedef struct mlmc_result {
     mlmc_level_stats level[MLMC_MAX_LEVELS];
 } mlmc_result;
 
+/* Who drives the estimates' sweeps.  1 (the default): the device sweep engine --
+ * each option's run state (level sums, sample counts = the next path index of each
+ * uniform stream, the driver's decisions) stays in device memory; one sweep of all
+ * options is one replay of a HIP graph that computes every run's next samples
+ * (pilot, per-level estimator, optimal allocation, bias test) on the device, plans
+ * their tiles, runs the path kernels and adds each work's fixed-order sums into its
+ * run; the host only replays it, prepares the levels a run reaches and collects
+ * finished runs.  0: the host computes each sweep's works from downloaded sums and
+ * launches them (a launch sequence per sweep).  Both give the same results bit for
+ * bit (same decisions on the same sums, same tiles, same reductions).  A workspace
+ * too small for the engine's arrays falls back to host-driven sweeps.  Errors:
+ * MLMC_E_INVALID, MLMC_E_BUSY (a server is running). */
+mlmc_status mlmc_set_driver(mlmc_context* ctx, int32_t engine);
+
 /* One option, one payoff (single bit of payoff_mask).  Errors as
  * mlmc_level_sums plus MLMC_E_INVALID for the run config. */
 mlmc_status mlmc_estimate(mlmc_context* ctx, const mlmc_problem* prob,
@@ -452,6 +466,9 @@ typedef struct mlmc_server_stats {
     double plan_seconds;        /* scheduler: next samples, planning, upload, launch */
     double land_seconds;        /* scheduler: landing flights, adding their sums */
     double idle_seconds;        /* scheduler: waiting for a flight or a request */
+    uint32_t engine;            /* 1: runs on the device sweep engine (flights: sweeps) */
+    uint32_t slots;             /* requests the workspace admits at once */
+    uint64_t bytes_per_request; /* engine: device bytes one admitted request holds */
 } mlmc_server_stats;
 
 /* out->struct_size must be set.  Errors: MLMC_E_BUSY (no server), MLMC_E_VERSION. */

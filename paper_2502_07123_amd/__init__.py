@@ -123,6 +123,10 @@ class Context:
         check(lib().mlmc_autotune(self.h, batch.n, batch._works, reps, C.byref(t)), self.h)
         return t.as_dict()
 
+    def set_driver(self, engine=True):
+        """Estimates' sweeps on the device sweep engine (True) or planned on the host."""
+        check(lib().mlmc_set_driver(self.h, 1 if engine else 0), self.h)
+
     def set_timing(self, on=True):
         check(lib().mlmc_set_timing(self.h, 1 if on else 0), self.h)
 

@@ -189,7 +189,8 @@ class ServerStats(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("pad", C.c_uint32), ("flights", C.c_uint64),
                 ("works", C.c_uint64), ("requests_done", C.c_uint64), ("queued", C.c_uint64),
                 ("active", C.c_uint64), ("plan_seconds", C.c_double), ("land_seconds", C.c_double),
-                ("idle_seconds", C.c_double)]
+                ("idle_seconds", C.c_double), ("engine", C.c_uint32), ("slots", C.c_uint32),
+                ("bytes_per_request", C.c_uint64)]
 
 
 class Request(C.Structure):
@@ -224,6 +225,7 @@ def lib():
         "mlmc_level_sums_enqueue": (st, [vp, u32, P(LevelWork), P(u64)]),
         "mlmc_level_sums_wait": (st, [vp, u64]),
         "mlmc_set_timing": (st, [vp, i32]),
+        "mlmc_set_driver": (st, [vp, i32]),
         "mlmc_get_tuning": (st, [vp, P(Tuning)]),
         "mlmc_set_tuning": (st, [vp, P(Tuning)]),
         "mlmc_autotune": (st, [vp, u32, P(LevelWork), u32, P(Tuning)]),
@@ -263,7 +265,7 @@ def lib():
 EXPORTED = ("mlmc_abi_version", "mlmc_status_string", "mlmc_last_error", "mlmc_context_create",
             "mlmc_context_destroy", "mlmc_level_sums", "mlmc_level_sums_static", "mlmc_level_sums_batch",
             "mlmc_level_sums_enqueue", "mlmc_level_sums_wait", "mlmc_set_timing",
-            "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune",
+            "mlmc_get_tuning", "mlmc_set_tuning", "mlmc_autotune", "mlmc_set_driver",
             "mlmc_kernel_stats", "mlmc_estimate", "mlmc_estimate_batch",
             "mlmc_server_start", "mlmc_submit", "mlmc_poll", "mlmc_poll_done", "mlmc_server_stats_get",
             "mlmc_server_stop", "mlmc_error_model_compute", "mlmc_optimise_widths",

@@ -18,7 +18,7 @@ BUILD = os.path.join(os.path.dirname(PKG), "_build")
 LIB = os.path.join(PKG, "libmlmc.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "host_check.hip", "errmodel.hip", "static_entry.hip", "inverse_normal.hip", "runtime.cpp", "server.cpp",
+SOURCES = ["kernels.hip", "host_check.hip", "errmodel.hip", "static_entry.hip", "inverse_normal.hip", "engine_kernels.hip", "engine.cpp", "runtime.cpp", "server.cpp",
            "host/prepare.cpp", "host/widths.cpp", "host/choose.cpp"]
 
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall",

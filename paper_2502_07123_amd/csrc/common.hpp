@@ -44,6 +44,34 @@ __host__ __device__ __forceinline__ uint64_t group_span(int level, uint32_t wpb)
     return N / a * wpb;
 }
 
+// The tiles of one work: groups [g0, g1) (S stream positions each) in nt tiles of
+// `per` groups.  Groups per tile: about tile_steps path-steps, but small enough that
+// the work alone has min_tiles tiles (parallelism), and at most max_tiles tiles; a
+// function of the work and the geometry alone, so a work's sums do not depend on
+// its neighbours (the host planner and the device sweep engine share it).
+struct WorkSplit {
+    uint64_t g0, g1, per, nt;
+};
+
+__host__ __device__ inline WorkSplit split_groups(uint32_t tile_steps, uint32_t min_tiles, uint32_t block,
+                                                  uint64_t S, int level, uint64_t path_begin, uint64_t n,
+                                                  uint64_t max_tiles) {
+    WorkSplit sp;
+    const uint64_t G = S >> level;                             // paths per group
+    sp.g0 = path_begin / G;
+    sp.g1 = (path_begin + n - 1) / G + 1;
+    const uint64_t total = sp.g1 - sp.g0;
+    uint64_t ppt = tile_steps / (block * S);
+    if (ppt < 1) ppt = 1;
+    const uint64_t fill = (total + uint64_t(block) * min_tiles - 1) / (uint64_t(block) * min_tiles);
+    if (fill < ppt) ppt = fill;
+    if (ppt < 1) ppt = 1;
+    sp.per = uint64_t(block) * ppt;
+    if ((total + sp.per - 1) / sp.per > max_tiles) sp.per = (total + max_tiles - 1) / max_tiles;
+    sp.nt = (total + sp.per - 1) / sp.per;
+    return sp;
+}
+
 struct LevelDev {
     // exact side (FP64 constants of the level)
     double con1, con1c, con2, con3, k, b;

@@ -731,14 +731,30 @@ struct PathBody {
         if (FIXED) acc.sat += c * ax.nsat;
     }
 
-    // ---- the approximate estimator with a float table side above level 0: whole
-    // groups without a debug buffer.  Where a path starts and ends within the group is
-    // fixed by the level, so this loop places the initialisations and the final
-    // samples by construction instead of testing each step as the general code does
-    // (there the per-step tests become selects on every state variable).  The steps
-    // (table_step), samples (finish) and their order are the general code's, so the
-    // sums are the same bit for bit.  Power-of-two blocks of 4F positions only.
-    static constexpr bool FASTG = EST == MLMC_EST_APPROX && !FIXED && (WPB & (WPB - 1)) == 0;
+    // ---- the approximate estimator above level 0: whole groups without a debug
+    // buffer.  Where a path starts and ends within the group is fixed by the level, so
+    // this loop places the initialisations and the final samples by construction
+    // instead of testing each step as the general code does (there the per-step tests
+    // become selects on every state variable).  The steps (table_step, fixed_step),
+    // samples (finish) and their order are the general code's, so the sums are the
+    // same bit for bit.  Power-of-two blocks of 4F positions only.
+    static constexpr bool FASTG = EST == MLMC_EST_APPROX && (WPB & (WPB - 1)) == 0;
+
+    // one table step of the approximate side at stream position j of a block
+    __host__ __device__ __forceinline__ static void approx_step(const LevelDev& L, const void* tab, uint32_t k,
+                                                                bool odd, FSide<AT>& ap, XSide& ax) {
+        if constexpr (FIXED) {
+            const int2 e = static_cast<const int2*>(tab)[k];
+            fixed_step<MIL>(ax, e.x, e.y, L, true, odd, TRACK);
+        } else {
+            const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k];
+            table_step<MIL, AT>(ap, e.z, e.s, L, true, odd, TRACK);
+        }
+    }
+    __host__ __device__ __forceinline__ static void approx_init(const LevelDev& L, FSide<AT>& ap, XSide& ax) {
+        if constexpr (FIXED) ax.init(L);
+        else ap.init();
+    }
 
     // the 4F table indices of Philox block b, position by position
     __host__ __device__ __forceinline__ static void block_indices(const WorkDev& W, uint64_t b, int q,
@@ -762,9 +778,8 @@ struct PathBody {
         XSide ax;
 #pragma unroll
         for (int j = 0; j < WPB; ++j) {
-            if ((j & (N - 1)) == 0) ap.init();
-            const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k[j]];
-            table_step<MIL, AT>(ap, e.z, e.s, L, true, (j & 1) != 0, TRACK);
+            if ((j & (N - 1)) == 0) approx_init(L, ap, ax);
+            approx_step(L, tab, k[j], (j & 1) != 0, ap, ax);
             if ((j & (N - 1)) == N - 1) finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
         }
     }
@@ -777,15 +792,12 @@ struct PathBody {
         FSide<ExactT> ex;
         FSide<AT> ap;
         XSide ax;
-        ap.init();
+        approx_init(L, ap, ax);
         for (uint32_t ib = 0; ib < nblk; ++ib, ++b) {
             uint32_t k[WPB];
             block_indices(W, b, L.q, k);
 #pragma unroll
-            for (int j = 0; j < WPB; ++j) {
-                const TabPair<AT> e = static_cast<const TabPair<AT>*>(tab)[k[j]];
-                table_step<MIL, AT>(ap, e.z, e.s, L, true, (j & 1) != 0, TRACK);
-            }
+            for (int j = 0; j < WPB; ++j) approx_step(L, tab, k[j], (j & 1) != 0, ap, ax);
         }
         finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
     }

@@ -252,6 +252,7 @@ extern "C" mlmc_status mlmc_error_model_compute(mlmc_context* ctx, const mlmc_pr
     if (!ctx || !prob || !out) return MLMC_E_INVALID;
     if (out->struct_size != sizeof(mlmc_error_model)) return fail(ctx, MLMC_E_VERSION, "mlmc_error_model.struct_size mismatch");
     if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    if (ctx->ws_held) return fail(ctx, MLMC_E_BUSY, "a running server's sweep engine holds the workspace");
     std::string err;
     mlmc_status s = validate_problem(prob, err);
     if (s != MLMC_OK) return fail(ctx, s, err);

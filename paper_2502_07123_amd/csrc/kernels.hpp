@@ -96,9 +96,11 @@ VariantInfo variant_info(const Variant& v);   // fn == nullptr when not compiled
 // YTAB_MAX_ENTRIES payoff slots x entries) run in the level-0 kernel.
 bool has_level0_kernel(const Variant& v);
 
-// n_tiles tiles generated from n_wt work descriptors (tile_of)
+// counts[1] tiles generated from counts[0] work descriptors starting at
+// wtiles + counts[2] (tile_of); counts is device memory, read by the kernel (a
+// captured launch reads its sizes at run time)
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,
-                        hipStream_t st, const WorkTilesDev* wtiles, uint32_t n_wt, uint32_t n_tiles,
+                        hipStream_t st, const WorkTilesDev* wtiles, const uint32_t* counts,
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
                         SlotDev* slots);
 

@@ -5,6 +5,7 @@
 #include "runtime.hpp"
 
 #include "device/philox.hpp"
+#include "engine_host.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -18,6 +19,20 @@ namespace mlmc {
 double now_seconds() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+mlmc_status fail(mlmc_context* ctx, mlmc_status s, const std::string& msg);
+
+}  // namespace mlmc
+
+uint64_t mlmc_context::tune_key() const {
+    uint64_t h = 1469598103934665603ull;
+    const uint64_t f[] = {tune.block_table, tune.block_exact, tune.tile_steps, tune.blocks_per_cu, tune.min_tiles,
+                          ws_bytes, reinterpret_cast<uint64_t>(ws)};
+    for (uint64_t x : f) h = (h ^ x) * 1099511628211ull;
+    return h;
+}
+
+namespace mlmc {
 
 mlmc_status fail(mlmc_context* ctx, mlmc_status s, const std::string& msg) {
     if (ctx) {
@@ -68,6 +83,7 @@ struct LaunchGroup {
     std::vector<uint32_t> works;
     uint32_t w0 = 0, w1 = 0;        // its work-tile descriptors
     uint32_t n_tiles = 0, block = 0, lds = 0;
+    uint32_t cnt = 0;               // index of its (work descriptors, tiles) count pair
 };
 
 constexpr size_t MAX_FLIGHTS = 4;
@@ -146,23 +162,9 @@ uint32_t block_for(const Tuning& t, const Variant& v, const VariantInfo& vi) {
                               static_cast<uint32_t>(vi.max_block));
 }
 
-// Groups per tile: about tile_steps path-steps, but small enough that the work alone
-// has min_tiles tiles (parallelism), and at most max_tiles tiles; a function of the
-// work and the geometry alone, so a work's sums do not depend on its neighbours.
 WorkSplit split_work(const Tuning& t, uint32_t block, uint64_t S, int level, uint64_t path_begin, uint64_t n,
                      uint64_t max_tiles) {
-    WorkSplit sp;
-    const uint64_t G = S >> level;                             // paths per group
-    sp.g0 = path_begin / G;
-    sp.g1 = (path_begin + n - 1) / G + 1;
-    const uint64_t total = sp.g1 - sp.g0;
-    uint64_t ppt = std::max<uint64_t>(1, t.tile_steps / (block * S));
-    const uint64_t fill = (total + uint64_t(block) * t.min_tiles - 1) / (uint64_t(block) * t.min_tiles);
-    ppt = std::max<uint64_t>(1, std::min(ppt, fill));
-    sp.per = uint64_t(block) * ppt;
-    if ((total + sp.per - 1) / sp.per > max_tiles) sp.per = (total + max_tiles - 1) / max_tiles;
-    sp.nt = (total + sp.per - 1) / sp.per;
-    return sp;
+    return split_groups(t.tile_steps, t.min_tiles, block, S, level, path_begin, n, max_tiles);
 }
 
 // LDS of a work: its step table, plus the level-0 index histogram of the approximate
@@ -242,6 +244,7 @@ mlmc_status drain_flights(mlmc_context* ctx) {
 // it and launches the sequence.  Caller holds dev_mtx.
 mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works, Flight& f) {
     if (ctx->poisoned) return fail(ctx, MLMC_E_DEVICE, "context poisoned by an earlier device error");
+    if (ctx->ws_held) return fail(ctx, MLMC_E_BUSY, "a running server's sweep engine holds the workspace");
     HIPCHK(hipSetDevice(ctx->device));
 
     // 1. levels, tables, works
@@ -431,7 +434,17 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     const size_t o_red = align_up(o_tile + wtiles.size() * sizeof(WorkTilesDev), 256);
     const size_t o_nt0 = align_up(o_red + reds.size() * sizeof(ReduceDev), 256);
     const size_t o_nt1 = align_up(o_nt0 + ntiles[0].size() * sizeof(TileDev), 256);
-    const size_t o_end_plan = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
+    // per launch group: (work descriptors, tiles), read by its path kernel
+    std::vector<uint32_t> counts;
+    for (auto& kv : groups) {
+        kv.second.cnt = static_cast<uint32_t>(counts.size());
+        counts.push_back(kv.second.w1 - kv.second.w0);
+        counts.push_back(kv.second.n_tiles);
+        counts.push_back(0);                        // the kernel gets its own descriptors' address
+        counts.push_back(0);
+    }
+    const size_t o_cnt = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
+    const size_t o_end_plan = align_up(o_cnt + counts.size() * sizeof(uint32_t), 256);
     // the second stream reads its own copy of the plan (uploaded on that stream, so
     // neither stream waits for the other)
     const size_t o_copy = o_end_plan;
@@ -495,6 +508,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     std::memcpy(h + (o_red - o_lvl), reds.data(), reds.size() * sizeof(ReduceDev));
     if (!ntiles[0].empty()) std::memcpy(h + (o_nt0 - o_lvl), ntiles[0].data(), ntiles[0].size() * sizeof(TileDev));
     if (!ntiles[1].empty()) std::memcpy(h + (o_nt1 - o_lvl), ntiles[1].data(), ntiles[1].size() * sizeof(TileDev));
+    if (!counts.empty()) std::memcpy(h + (o_cnt - o_lvl), counts.data(), counts.size() * sizeof(uint32_t));
     hipStream_t s = ctx->stream;
     hipStream_t sa = fork ? ctx->aux_stream : s;
     hipError_t ue = launch_upload(h, d + o_lvl, up_bytes, s);
@@ -544,7 +558,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
             HIPCHK(hipEventRecord(tm.e0, gs));
         }
         HIPCHK(launch_paths(g.vi, grid, g.block, g.lds, gs,
-                            reinterpret_cast<const WorkTilesDev*>(dp + o_tile) + g.w0, g.w1 - g.w0, nt,
+                            reinterpret_cast<const WorkTilesDev*>(dp + o_tile) + g.w0,
+                            reinterpret_cast<const uint32_t*>(dp + o_cnt) + g.cnt,
                             reinterpret_cast<const WorkDev*>(dp + o_work),
                             reinterpret_cast<const LevelDev*>(dp + o_lvl), dp + o_tab,
                             reinterpret_cast<SlotDev*>(d + o_slot)));
@@ -594,147 +609,84 @@ mlmc_status run_works(mlmc_context* ctx, const std::vector<WorkSpec>& works, std
 }
 
 // ------------------------------------------------------------- adaptive MLMC
-// estimators a level uses: the nested pair, or plain (plain runs; levels switched
-// by the per-level choice below)
-static bool level_plain(const OptionRun& o, int l) { return !o.cfg.nested || o.plain_lv[l]; }
-static int n_est(const OptionRun& o, int l) { return level_plain(o, l) ? 1 : 2; }
-static int est_at(const OptionRun& o, int l, int i) {
-    return level_plain(o, l) ? MLMC_EST_PLAIN : (i == 0 ? MLMC_EST_APPROX : MLMC_EST_CORR);
+// The decisions (pilot, per-level estimator, allocation, bias test) are
+// run_advance's (device/advance.hpp), on the option's plain-data RunState.
+
+double option_eps(const mlmc_problem& prob, const mlmc_run_config& cfg) {
+    const double scale = std::exp(-prob.r * prob.T) * (cfg.eps_units == 1 ? prob.S0 : 1.0);
+    return cfg.eps / scale;
 }
-static double s_mean(const SlotDev& s) { return s.n ? s.s1[0] / static_cast<double>(s.n) : 0.0; }
-static double s_var(const SlotDev& s) {
-    if (s.n < 2) return 0.0;
-    const double n = static_cast<double>(s.n);
-    return std::max((s.s2[0] - s.s1[0] * s.s1[0] / n) / (n - 1.0), 0.0);       // R9
+
+void run_state_init(RunState& st, const mlmc_problem& prob, const mlmc_run_config& cfg) {
+    const double cost[3] = {cfg.cost_plain, cfg.cost_approx, cfg.cost_corr};
+    run_init(st, option_eps(prob, cfg), cfg.theta, cost, cfg.n_pilot, cfg.nested ? 1 : 0, cfg.L_min, cfg.L_max);
+}
+
+EstSums est_of_slot(const SlotDev& s) {
+    EstSums e;
+    e.n = s.n;
+    e.s1 = s.s1[0];
+    e.s2 = s.s2[0];
+    e.e1 = s.e1[0];
+    e.e2 = s.e2[0];
+    e.i1 = s.i1[0];
+    e.i2lo = s.i2lo[0];
+    e.i2hi = s.i2hi[0];
+    e.sat = s.sat;
+    e.nonfinite = s.nonfinite;
+    return e;
 }
 
 void option_init(OptionRun& o) {
-    o.L = o.cfg.L_min;
-    o.done = false;
-    o.sweeps = 0;
-    o.path_steps = 0;
+    run_state_init(o.st, o.prob, o.cfg);
     o.saturations = 0;
-    o.sums.assign(static_cast<size_t>(o.cfg.L_max) + 1, std::array<SlotDev, 3>{});
-    for (auto& a : o.sums) for (auto& s : a) std::memset(&s, 0, sizeof(s));
-    o.plain_lv.assign(static_cast<size_t>(o.cfg.L_max) + 1, 0);
-    o.decided.assign(static_cast<size_t>(o.cfg.L_max) + 1, 0);
     o.t_start = now_seconds();
-}
-
-static double eps_internal(const OptionRun& o) {
-    const double scale = std::exp(-o.prob.r * o.prob.T) * (o.cfg.eps_units == 1 ? o.prob.S0 : 1.0);
-    return o.cfg.eps / scale;
-}
-
-static double est_cost(const OptionRun& o, int est) {
-    return est == MLMC_EST_PLAIN ? o.cfg.cost_plain
-                                 : (est == MLMC_EST_APPROX ? o.cfg.cost_approx : o.cfg.cost_corr);
-}
-
-// Remaining bias after level L (R34, Giles' MLMC test): the last three correction
-// levels, max over l = max(1, L-2) .. L of |mean_l| 2^(alpha (l - L)), over
-// 2^alpha - 1, with alpha = 1, the weak order of both schemes (Section 2.1).
-static double remaining_bias(const std::vector<double>& m) {
-    constexpr double alpha = 1.0;
-    const int L = static_cast<int>(m.size()) - 1;
-    const int lo = L >= 1 ? std::max(1, L - 2) : 0;
-    double r = 0.0;
-    for (int l = lo; l <= L; ++l) r = std::max(r, std::fabs(m[l]) * std::pow(2.0, alpha * (l - L)));
-    return r / (std::pow(2.0, alpha) - 1.0);
+    o.t_end = 0.0;
 }
 
 std::vector<Pending> option_advance(OptionRun& o) {
     std::vector<Pending> pend;
-    if (o.done) return pend;
-    for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < n_est(o, l); ++i) {
-            const int e = est_at(o, l, i);
-            const uint64_t have = o.sums[l][e].n;
-            if (have < o.cfg.n_pilot) pend.push_back({l, e, o.cfg.n_pilot - have});
-        }
-    if (!pend.empty()) return pend;
-    // per-level estimator (R35, once per level after its pilot): the nested pair only
-    // while it is cheaper than plain samples, (sqrt(V~ c~) + sqrt(V^D c^D))^2 <= V~ c
-    if (o.cfg.nested) {
-        for (int l = 0; l <= o.L; ++l) {
-            if (o.decided[l]) continue;
-            o.decided[l] = 1;
-            if (o.plain_lv[l]) continue;
-            const double Va = std::max(s_var(o.sums[l][MLMC_EST_APPROX]), 1e-300);
-            const double Vc = std::max(s_var(o.sums[l][MLMC_EST_CORR]), 1e-300);
-            const double root = std::sqrt(Va * o.cfg.cost_approx) + std::sqrt(Vc * o.cfg.cost_corr);
-            if (root * root > Va * o.cfg.cost_plain) {
-                o.plain_lv[l] = 1;
-                std::memset(&o.sums[l][MLMC_EST_APPROX], 0, sizeof(SlotDev));
-                std::memset(&o.sums[l][MLMC_EST_CORR], 0, sizeof(SlotDev));
-                pend.push_back({l, MLMC_EST_PLAIN, o.cfg.n_pilot});
-            }
-        }
-        if (!pend.empty()) return pend;
-    }
-    const double eps = eps_internal(o);
-    // optimal allocation over all (level, estimator) pairs with one multiplier
-    double lam = 0.0;
-    for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < n_est(o, l); ++i) {
-            const int e = est_at(o, l, i);
-            const double V = std::max(s_var(o.sums[l][e]), 1e-300);
-            lam += std::sqrt(V * est_cost(o, e) * std::ldexp(1.0, l));
-        }
-    lam /= o.cfg.theta * eps * eps;
-    for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < n_est(o, l); ++i) {
-            const int e = est_at(o, l, i);
-            const double V = std::max(s_var(o.sums[l][e]), 1e-300);
-            const double target = std::ceil(lam * std::sqrt(V / (est_cost(o, e) * std::ldexp(1.0, l))));
-            const uint64_t t = target > 1.8e19 ? UINT64_MAX : static_cast<uint64_t>(target);
-            if (t > o.sums[l][e].n) pend.push_back({l, e, t - o.sums[l][e].n});
-        }
-    if (!pend.empty()) return pend;
-    std::vector<double> means(o.L + 1, 0.0);
-    for (int l = 0; l <= o.L; ++l)
-        for (int i = 0; i < n_est(o, l); ++i) means[l] += s_mean(o.sums[l][est_at(o, l, i)]);
-    if (remaining_bias(means) > std::sqrt(1.0 - o.cfg.theta) * eps && o.L < o.cfg.L_max) {
-        o.L += 1;
-        // a new level above a plain level l >= 1 starts plain
-        if (o.cfg.nested && o.L - 1 >= 1 && o.plain_lv[o.L - 1]) {
-            o.plain_lv[o.L] = 1;
-            o.decided[o.L] = 1;
-        }
-        for (int i = 0; i < n_est(o, o.L); ++i) pend.push_back({o.L, est_at(o, o.L, i), o.cfg.n_pilot});
-        return pend;
-    }
-    o.done = true;
-    o.t_end = now_seconds();
+    if (o.st.done) return pend;
+    run_advance(o.st);
+    for (int i = 0; i < o.st.n_pend; ++i) pend.push_back({o.st.pend[i].level, o.st.pend[i].est, o.st.pend[i].n});
+    if (o.st.done) o.t_end = now_seconds();
     return pend;
 }
 
-void option_result(const OptionRun& o, mlmc_result& r) {
+void result_of_state(const RunState& st, const mlmc_problem& prob, const mlmc_run_config& cfg, double seconds,
+                     mlmc_result& r) {
     std::memset(&r, 0, sizeof(r));
     r.struct_size = sizeof(mlmc_result);
-    r.status = o.done ? MLMC_OK : MLMC_PENDING;
-    r.L = o.L;
-    r.sweeps = o.sweeps;
-    const double sc = std::exp(-o.prob.r * o.prob.T) * o.prob.S0;       // R4, R5a
+    r.status = st.done ? MLMC_OK : MLMC_PENDING;
+    r.L = st.L;
+    r.sweeps = st.sweeps;
+    const double sc = std::exp(-prob.r * prob.T) * prob.S0;       // R4, R5a
     double est = 0.0, var = 0.0;
-    for (int l = 0; l <= o.L; ++l)
+    uint64_t sat = 0;
+    for (int l = 0; l < MLMC_MAX_LEVELS; ++l)
+        for (int e = 0; e < 3; ++e) sat += st.sums[l][e].sat;
+    for (int l = 0; l <= st.L; ++l)
         for (int e = 0; e < 3; ++e) {
-            const SlotDev& s = o.sums[l][e];
+            const EstSums& s = st.sums[l][e];
             r.level[l].n[e] = s.n;
-            r.level[l].mean[e] = s_mean(s);
-            r.level[l].var[e] = s_var(s);
+            r.level[l].mean[e] = est_mean(s);
+            r.level[l].var[e] = est_var(s);
             if (s.n) {
-                est += s_mean(s);
-                var += s_var(s) / static_cast<double>(s.n);
-                if (e == MLMC_EST_CORR) r.exact_sides |= o.cfg.prec[l].exact_side == 1 ? 2 : 1;
+                est += est_mean(s);
+                var += est_var(s) / static_cast<double>(s.n);
+                if (e == MLMC_EST_CORR) r.exact_sides |= cfg.prec[l].exact_side == 1 ? 2 : 1;
                 if (e == MLMC_EST_PLAIN) r.exact_sides |= 4;
             }
         }
     r.estimate = sc * est;
     r.variance = sc * sc * var;
-    r.seconds = o.t_end - o.t_start;
-    r.path_steps = o.path_steps;
-    r.saturations = o.saturations;
+    r.seconds = seconds;
+    r.path_steps = st.path_steps;
+    r.saturations = sat;
+}
+
+void option_result(const OptionRun& o, mlmc_result& r) {
+    result_of_state(o.st, o.prob, o.cfg, o.t_end - o.t_start, r);
 }
 
 static mlmc_precision plain_precision(const OptionRun& o) {
@@ -800,7 +752,7 @@ mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, b
     std::vector<std::pair<size_t, Pending>> who;
     for (size_t i = 0; i < opts.size(); ++i) {
         OptionRun& o = *opts[i];
-        if (o.done) continue;
+        if (o.st.done) continue;
         plain[i] = plain_precision(o);
         for (const Pending& p : option_advance(o)) {
             WorkSpec w;
@@ -810,7 +762,7 @@ mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, b
             w.est = p.est;
             w.seed = o.seed;
             w.option = o.option;
-            w.path_begin = o.sums[p.level][p.est].n;
+            w.path_begin = o.st.sums[p.level][p.est].n;
             w.n = p.n;
             w.debug = 0;
             std::string err;
@@ -829,13 +781,9 @@ mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, b
     for (size_t k = 0; k < works.size(); ++k) {
         OptionRun& o = *opts[who[k].first];
         const Pending& p = who[k].second;
-        slot_accumulate(o.sums[p.level][p.est], res[k]);
-        o.path_steps += p.n << p.level;
-        if (!counted[who[k].first]) { o.sweeps += 1; counted[who[k].first] = true; }
-    }
-    for (OptionRun* o : opts) {
-        o->saturations = 0;
-        for (auto& l : o->sums) for (auto& x : l) o->saturations += x.sat;
+        est_accumulate(o.st.sums[p.level][p.est], est_of_slot(res[k]));
+        o.st.path_steps += p.n << p.level;
+        if (!counted[who[k].first]) { o.st.sweeps += 1; counted[who[k].first] = true; }
     }
     return MLMC_OK;
 }
@@ -899,7 +847,22 @@ mlmc_status estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* pr
         runs[i].t_start = t0;
         ptrs[i] = &runs[i];
     }
-    const mlmc_status s = run_sweeps(ctx, ptrs);
+    if (ctx->ws_held) return fail(ctx, MLMC_E_BUSY, "a running server's sweep engine holds the workspace");
+    mlmc_status s = MLMC_E_NOMEM;
+    if (ctx->driver == 1) {
+        // the device sweep engine owns the workspace while it runs
+        std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+        s = drain_flights(ctx);
+        if (s == MLMC_OK || !ctx->poisoned) s = engine_run_batch(ctx, runs);
+    }
+    if (s == MLMC_E_NOMEM) {
+        // a workspace too small for the engine: sweeps planned on the host
+        for (uint32_t i = 0; i < n; ++i) {
+            option_init(runs[i]);
+            runs[i].t_start = t0;
+        }
+        s = run_sweeps(ctx, ptrs);
+    }
     if (s != MLMC_OK) return s;
     for (uint32_t i = 0; i < n; ++i) option_result(runs[i], out[i]);
     return MLMC_OK;
@@ -975,6 +938,7 @@ void mlmc_context_destroy(mlmc_context* ctx) {
     {
         std::lock_guard<std::mutex> lock(ctx->dev_mtx);
         (void)drain_flights(ctx);
+        ctx->engines.clear();
     }
     if (ctx->aux_stream) (void)hipStreamSynchronize(ctx->aux_stream);
     for (hipEvent_t e : ctx->ev_plain) (void)hipEventDestroy(e);
@@ -1207,6 +1171,15 @@ mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* 
     }
     if (r != MLMC_OK) return r;
     return mlmc_get_tuning(ctx, out);
+}
+
+mlmc_status mlmc_set_driver(mlmc_context* ctx, int32_t engine) {
+    if (!ctx) return MLMC_E_INVALID;
+    if (engine != 0 && engine != 1) return fail(ctx, MLMC_E_INVALID, "driver must be 0 (host) or 1 (device engine)");
+    if (ctx->server) return fail(ctx, MLMC_E_BUSY, "a server is running");
+    std::lock_guard<std::mutex> lock(ctx->dev_mtx);
+    ctx->driver = engine;
+    return MLMC_OK;
 }
 
 mlmc_status mlmc_set_timing(mlmc_context* ctx, int32_t on) {

@@ -16,6 +16,7 @@
 
 #include "../../include/mlmc.h"
 #include "common.hpp"
+#include "device/advance.hpp"
 #include "host/prepare.hpp"
 #include "kernels.hpp"
 
@@ -50,11 +51,6 @@ bool level0_kernel_for(const Variant& v, int level, bool debug, const LevelDev& 
 // Threads per block of a kernel variant under a geometry.
 uint32_t block_for(const Tuning& t, const Variant& v, const VariantInfo& vi);
 
-// The tiles of one work: groups [g0, g1) (S stream positions each) in nt tiles of
-// `per` groups.
-struct WorkSplit {
-    uint64_t g0, g1, per, nt;
-};
 constexpr uint64_t FLIGHT_MAX_TILES = uint64_t(1) << 16;
 WorkSplit split_work(const Tuning& t, uint32_t block, uint64_t S, int level, uint64_t path_begin, uint64_t n,
                      uint64_t max_tiles);
@@ -76,6 +72,7 @@ struct WorkSpec {
 };
 
 struct Server;
+struct Engine;
 
 struct PinnedBuf {
     uint8_t* p = nullptr;
@@ -122,6 +119,12 @@ struct mlmc_context {
     mlmc::Tuning tune;
     std::mutex dev_mtx;             // one launch sequence at a time on the device
     std::unique_ptr<mlmc::Server> server;
+    // device sweep engines of recent batches of estimates (kept for their graphs;
+    // each lays its arrays over the workspace while it runs)
+    std::vector<std::unique_ptr<mlmc::Engine>> engines;
+    int driver = 1;                 // estimates: 1 device sweep engine, 0 host-driven sweeps
+    bool ws_held = false;           // a server's sweep engine holds the workspace
+    uint64_t tune_key() const;      // the launch geometry, as one number
     // per-context cache of prepared levels (key: problem, level, precision, estimator)
     std::map<std::string, mlmc::LevelPrep> prep_cache;
     // launch sequences in flight (oldest first) and statuses of landed tickets
@@ -167,18 +170,20 @@ struct OptionRun {
     mlmc_run_config cfg;
     uint64_t seed = 0;
     uint32_t option = 0;
-    int L = 0;
-    bool done = false;
-    int sweeps = 0;
+    RunState st;                                // sums, levels, decisions (device/advance.hpp)
     double t_start = 0.0, t_end = 0.0;
-    uint64_t path_steps = 0;
     uint64_t saturations = 0;
-    std::vector<std::array<SlotDev, 3>> sums;   // host copy per level, estimator
-    std::vector<uint8_t> plain_lv;              // nested runs: level switched to plain
-    std::vector<uint8_t> decided;               // nested runs: level's estimator chosen
     // levels prepared for this option (constants, table, variant), per estimator
     std::vector<std::array<std::shared_ptr<const LevelPrep>, 3>> preps;
 };
+
+// The option's normalised eps (eps_units) and its RunState's initial values.
+double option_eps(const mlmc_problem& prob, const mlmc_run_config& cfg);
+void run_state_init(RunState& st, const mlmc_problem& prob, const mlmc_run_config& cfg);
+// The payoff slot 0 of a work's result as EstSums.
+EstSums est_of_slot(const SlotDev& s);
+void result_of_state(const RunState& st, const mlmc_problem& prob, const mlmc_run_config& cfg, double seconds,
+                     mlmc_result& r);
 
 void option_init(OptionRun& o);
 // Pending (level, estimator, extra samples) of an option, or none when done.

@@ -150,13 +150,14 @@ extern "C" mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t 
     const WorkSplit sp = split_work(tune, block, S, level, path_offset, n_paths, STATIC_MAX_TILES);
     const uint32_t lds = lds_bytes_for(lp.variant, lp.dev);
 
-    // layout: [result | level | work | work tiles | reduction | table | tile slots]
+    // layout: [result | level | work | work tiles | reduction | counts | table | tile slots]
     const size_t o_res = 0;
     const size_t o_lvl = align256(o_res + sizeof(SlotDev));
     const size_t o_work = align256(o_lvl + sizeof(LevelDev));
     const size_t o_tile = align256(o_work + sizeof(WorkDev));
     const size_t o_red = align256(o_tile + sizeof(WorkTilesDev));
-    const size_t o_tab = align256(o_red + sizeof(ReduceDev));
+    const size_t o_cnt = align256(o_red + sizeof(ReduceDev));
+    const size_t o_tab = align256(o_cnt + 4 * sizeof(uint32_t));
     const size_t o_slot = align256(o_tab + lp.table.size());
     const size_t need = o_slot + sp.nt * sizeof(SlotDev);
     if (sp.nt > STATIC_MAX_TILES || need > SCRATCH_BYTES)
@@ -192,13 +193,15 @@ extern "C" mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t 
 
     // one host buffer [level .. table] on the stack, sent as kernel arguments
     uint8_t plan[align256(sizeof(LevelDev)) + align256(sizeof(WorkDev)) + align256(sizeof(WorkTilesDev)) +
-                 align256(sizeof(ReduceDev))];
+                 align256(sizeof(ReduceDev)) + 256];
     if (o_tab - o_lvl > sizeof(plan)) return static_fail(MLMC_E_INVALID, "plan header layout");
     std::memset(plan, 0, sizeof(plan));
     std::memcpy(plan + (o_lvl - o_lvl), &L, sizeof(L));
     std::memcpy(plan + (o_work - o_lvl), &W, sizeof(W));
     std::memcpy(plan + (o_tile - o_lvl), &wt, sizeof(wt));
     std::memcpy(plan + (o_red - o_lvl), &rd, sizeof(rd));
+    const uint32_t counts[4] = {1u, static_cast<uint32_t>(sp.nt), 0u, 0u};  // work descriptors, tiles
+    std::memcpy(plan + (o_cnt - o_lvl), counts, sizeof(counts));
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t* d = sd.ptr;
@@ -207,8 +210,8 @@ extern "C" mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t 
     if (e != hipSuccess) return static_fail(MLMC_E_DEVICE, std::string("plan: ") + hipGetErrorString(e));
     const uint32_t grid = static_cast<uint32_t>(
         std::min<uint64_t>(sp.nt, uint64_t(std::max(1, sd.cus)) * tune.blocks_per_cu));
-    e = launch_paths(vi, grid, block, lds, st, reinterpret_cast<const WorkTilesDev*>(d + o_tile), 1,
-                     static_cast<uint32_t>(sp.nt), reinterpret_cast<const WorkDev*>(d + o_work),
+    e = launch_paths(vi, grid, block, lds, st, reinterpret_cast<const WorkTilesDev*>(d + o_tile),
+                     reinterpret_cast<const uint32_t*>(d + o_cnt), reinterpret_cast<const WorkDev*>(d + o_work),
                      reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab,
                      reinterpret_cast<SlotDev*>(d + o_slot));
     if (e == hipSuccess)

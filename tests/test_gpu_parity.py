@@ -122,7 +122,7 @@ def test_repeatable_and_offset_split(ctx):
 
 
 @pytest.mark.parametrize("arith,q,packed", [("fp32", 8, True), ("fp32", 4, True), ("fp32", 8, False),
-                                            ("fp16", 8, True)])
+                                            ("fp16", 8, True), ("fixed", 8, False)])
 def test_approx_group_loop_equals_debug_run(ctx, arith, q, packed):
     """Levels >= 1 of the approximate estimator without a debug buffer run whole groups
     through a loop with path boundaries placed by construction: the same sums as the
@@ -130,7 +130,7 @@ def test_approx_group_loop_equals_debug_run(ctx, arith, q, packed):
     payoff and all five (path functionals)."""
     for pays in (("euro",), PAYS):
         prob = M.make_problem("milstein", pays, **GBM)
-        prec = M.make_precision(arith, q, packed)
+        prec = M.make_precision(arith, q, packed, WIDE_FMT if arith == "fixed" else None)
         for level in (1, 2, 3, 4, 6):
             n = (1 << 21) // (1 << level) + 7
             a = ctx.level_sums(prob, level, n, 9, prec, M.EST_APPROX, SEED)

@@ -148,3 +148,22 @@ def test_method2_correction_group_loop():
         for name in PAYS:
             for f in ("n", "sum1", "sum2", "esum1", "esum2"):
                 assert fast[name][f] == slow[name][f], (name, f, level)
+
+
+@pytest.mark.parametrize("scheme", ["euler", "milstein"])
+@pytest.mark.parametrize("arith,q,packed", [("fixed", 8, False), ("fp32", 8, True), ("fp16", 8, True)])
+def test_approx_group_loop_equals_per_path_code(scheme, arith, q, packed):
+    """Levels >= 1 of the approximate estimator without records run whole groups with
+    path boundaries by construction: the same sums as the per-path code (exact
+    integers for fixed point), ragged ends included."""
+    fmt = WIDE_FMT if arith == "fixed" else None
+    for pays in (("euro",), PAYS):
+        prob = M.make_problem(scheme, pays, **GBM)
+        prec = M.make_precision(arith, q, packed, fmt)
+        for level in (1, 2, 3, 5):
+            n = 3001
+            fast, _ = M.check_paths_host(prob, level, n, 7, prec, EST_APPROX, SEED, records=False)
+            slow, _ = M.check_paths_host(prob, level, n, 7, prec, EST_APPROX, SEED)
+            for name in pays:
+                for f in ("n", "sum1", "sum2", "isum1", "isum2", "saturations", "nonfinite"):
+                    assert fast[name][f] == slow[name][f], (level, name, f)
