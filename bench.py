@@ -239,6 +239,9 @@ def main():
                     help="launch geometry as JSON (fields of mlmc_tuning) in place of the tuner")
     ap.add_argument("--per-level", action="store_true",
                     help="instead: path-steps/s per level for each kernel class")
+    ap.add_argument("--fixed-sweep", action="store_true",
+                    help="instead: the fixed-point workload (Euler, 1e6 paths per level, levels 0..10, "
+                         "European + Asian + barrier on the same paths)")
     args = ap.parse_args()
     if not 1 <= args.depth <= 4:
         ap.error("--depth must be 1..4")
@@ -247,7 +250,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.batch or args.serving or args.per_level:
+    if args.batch or args.serving or args.per_level or args.fixed_sweep:
         return main_workloads(args)
     pool, P = (None, 1) if args.no_cpu else oracle_pool()
     import numpy as np
@@ -751,6 +754,48 @@ def per_level(M, ctx, steps_per_work=1 << 27, reps=3):
     return out
 
 
+def fixed_sweep(M, ctx, n_paths=1_000_000, reps=3):
+    """The fixed-point workload: Euler paths with X a signed 32-bit Q-format number
+    of b_l = min(24, 14 + l) fractional bits (the other variables' formats those of
+    the parity tests), the q = 8 table in Z's format, European, Asian and barrier (85)
+    payoffs of the same paths in one launch, 1e6 paths at each level 0..10.  Per
+    level: path kernel time (HIP events, mean of reps), path-steps/s and saturations;
+    the whole sweep: the sum of the levels' kernel times and its wall time."""
+    import torch
+    base = {"X": (32, 22), "con1": (32, 34), "con2": (32, 33), "con3": (32, 36), "Z": (31, 28),
+            "mul1": (32, 30), "sum1": (32, 30), "zsq": (32, 23), "zm1": (32, 23), "mul3": (32, 29),
+            "sum2": (32, 29), "mul2": (32, 27)}
+    prob = M.make_problem("euler", ("euro", "asian", "barrier"), **GBM)
+    precs = [M.make_precision("fixed", 8, False, {**base, "X": (32, min(24, 14 + l))}) for l in range(11)]
+    for l in range(11):
+        ctx.level_sums(prob, l, n_paths, 0, precs[l], M.EST_APPROX, SEED)          # warm
+    rows, kernel_ms = [], 0.0
+    for l in range(11):
+        ctx.set_timing(True)
+        for r in range(reps):
+            sums = ctx.level_sums(prob, l, n_paths, 0, precs[l], M.EST_APPROX, SEED)
+        st = ctx.kernel_stats()
+        ctx.set_timing(False)
+        ms = sum(x["ms"] for x in st) / reps
+        kernel_ms += ms
+        rows.append({"level": l, "b": min(24, 14 + l), "kernel_ms": ms,
+                     "path_steps_per_s": (n_paths << l) / (ms * 1e-3),
+                     "saturations": int(sum(s["saturations"] for s in sums.values()))})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        for l in range(11):
+            ctx.level_sums(prob, l, n_paths, 0, precs[l], M.EST_APPROX, SEED)
+    wall = (time.perf_counter() - t0) / reps
+    steps = sum(n_paths << l for l in range(11))
+    out = {"workload": "fixed-point Euler, 1e6 paths/level, levels 0..10, euro+asian+barrier(85)",
+           "levels": rows, "sweep_kernel_ms": kernel_ms, "sweep_wall_ms": wall * 1e3,
+           "path_steps": steps, "path_steps_per_s_kernel": steps / (kernel_ms * 1e-3),
+           "path_steps_per_s_wall": steps / wall}
+    print(json.dumps({"fixed_sweep": out}), file=sys.stderr, flush=True)
+    return out
+
+
 def main_workloads(args):
     """--batch / --serving: one JSON line with the batched and/or served workloads."""
     import torch
@@ -770,6 +815,8 @@ def main_workloads(args):
         ctx.set_driver(True)
     if args.per_level:
         line["per_level_path_steps_per_s"] = per_level(M, ctx)
+    if args.fixed_sweep:
+        line["fixed_sweep"] = fixed_sweep(M, ctx)
     torch.cuda.synchronize()
     print(json.dumps(line))
     ctx.close()

@@ -110,7 +110,7 @@ typedef struct mlmc_problem {
  *                destination's f, to nearest with ties toward +infinity, then
  *                saturated to w bits (saturations are counted).  The table entries
  *                use Z's format; the coarse sum of two normals keeps Z's f with one
- *                more integer bit; constants and k, b are quantised exactly from
+ *                more integer bit; X's format must hold X_0 = 1 (f <= w - 2); constants and k, b are quantised exactly from
  *                their FP64 values (con1 = r h, con2 = sigma * sqrt(h),
  *                con3 = ((0.5 * sigma) * sigma) * h, k = K / S0, b = B / S0).
  *   rng_method   APPROX/CORR: the approximate normals of Section 3 (0 or 1:

@@ -227,12 +227,15 @@ __host__ __device__ __forceinline__ void table_step(FSide<T>& s, T z, T sk, cons
 }
 
 // ----------------------------------------------------------------- fixed side
+// Path variables are 32-bit words (saturated to their w <= 32 bits); the Asian sums
+// of X over the grid are exact 64-bit integers.
 struct XSide {
-    int64_t xf, xc, af, ac, mf, mc, zp;
+    int32_t xf, xc, mf, mc, zp;
+    int64_t af, ac;
     uint32_t nsat;
 
     __host__ __device__ __forceinline__ void init(const LevelDev& L) {
-        xf = xc = mf = mc = int64_t(1) << L.fX;
+        xf = xc = mf = mc = static_cast<int32_t>(int64_t(1) << L.fX);
         af = ac = 0;
         zp = 0;
         nsat = 0;
@@ -259,28 +262,31 @@ struct XSide {
     }
 };
 
+// Algorithm 1's fine step X <- X + X s_k (s_k tabulated per index) and, once per
+// fine pair, the coarse chain on Zs = Z_2m + Z_2m+1, every operation in the 32-bit
+// forms of device/fixed.hpp.
 template <bool MIL>
-__host__ __device__ __forceinline__ void fixed_step(XSide& s, int64_t z, int64_t sk,
+__host__ __device__ __forceinline__ void fixed_step(XSide& s, int32_t z, int32_t sk,
                                                     const LevelDev& L, bool coarse_on, bool odd,
                                                     bool track) {
-    const int64_t m2 = fx_mul(s.xf, sk, L.op_mul2, s.nsat);
-    s.xf = fx_add(s.xf, m2, L.op_addX, s.nsat);
+    const int32_t m2 = fx32_mul(s.xf, sk, L.op_mul2, s.nsat);
+    s.xf = fx32_add(s.xf, m2, L.op_addX, s.nsat);
     if (track) { s.af += s.xf; s.mf = s.xf < s.mf ? s.xf : s.mf; }
     if (coarse_on) {
         if (!odd) {
             s.zp = z;
         } else {
-            const int64_t zs = s.zp + z;                       // exact, one more integer bit
-            const int64_t m1 = fx_mul(L.icon2, zs, L.op_mul1, s.nsat);
-            int64_t sc = fx_add(L.icon1c, m1, L.op_sum1, s.nsat);
+            const int32_t zs = s.zp + z;                       // exact: Z has at most 31 bits
+            const int32_t m1 = fx32_mul(static_cast<int32_t>(L.icon2), zs, L.op_mul1, s.nsat);
+            int32_t sc = fx32_add(static_cast<int32_t>(L.icon1c), m1, L.op_sum1, s.nsat);
             if (MIL) {
-                const int64_t zq = fx_mul(zs, zs, L.op_zsq, s.nsat);
-                const int64_t zm = fx_add(zq, -L.izm_c2, L.op_zm1, s.nsat);
-                const int64_t m3 = fx_mul(L.icon3, zm, L.op_mul3, s.nsat);
-                sc = fx_add(sc, m3, L.op_sum2, s.nsat);
+                const int32_t zq = fx32_mul(zs, zs, L.op_zsq, s.nsat);
+                const int32_t zm = fx32_add(zq, static_cast<int32_t>(-L.izm_c2), L.op_zm1, s.nsat);
+                const int32_t m3 = fx32_mul(static_cast<int32_t>(L.icon3), zm, L.op_mul3, s.nsat);
+                sc = fx32_add(sc, m3, L.op_sum2, s.nsat);
             }
-            const int64_t m2c = fx_mul(s.xc, sc, L.op_mul2, s.nsat);
-            s.xc = fx_add(s.xc, m2c, L.op_addX, s.nsat);
+            const int32_t m2c = fx32_mul(s.xc, sc, L.op_mul2, s.nsat);
+            s.xc = fx32_add(s.xc, m2c, L.op_addX, s.nsat);
             if (track) { s.ac += s.xc; s.mc = s.xc < s.mc ? s.xc : s.mc; }
         }
     }

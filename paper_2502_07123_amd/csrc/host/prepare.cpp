@@ -370,6 +370,8 @@ mlmc_status validate_precision(const mlmc_precision* prec, int estimator, const 
         if (w[v] < 2 || w[v] > wmax) { err = "word_bits out of range (2..32, Z 2..31) for variable " + std::to_string(v); return MLMC_E_INVALID; }
         if (f[v] < 0 || f[v] > 62) { err = "frac_bits out of range (0..62) for variable " + std::to_string(v); return MLMC_E_INVALID; }
     }
+    // X_0 = 1 must be a value of X's format (the path starts there unsaturated)
+    if (f[MLMC_V_X] > w[MLMC_V_X] - 2) { err = "X's format must hold 1: frac_bits[X] <= word_bits[X] - 2"; return MLMC_E_INVALID; }
     auto mul_ok = [&](int a, int b, int d) { return f[a] + f[b] - f[d] >= 0 && f[a] + f[b] - f[d] <= 62; };
     auto add_ok = [&](int a, int b, int d) {
         const int fm = std::max(f[a], f[b]);
@@ -404,14 +406,14 @@ mlmc_status validate_all(const mlmc_problem* p, int32_t level, uint64_t n_paths,
 
 // --------------------------------------------------------------- level prep
 static FxOp mul_op(const int* f, const int* w, int a, int b, int d) {
-    return FxOp{0, 0, f[a] + f[b] - f[d], w[d]};
+    return fx_op_finish(FxOp{0, 0, f[a] + f[b] - f[d], w[d], 0, 0, 0, 0, 0});
 }
 static FxOp mul_op_fz(const int* f, const int* w, int fa, int fb, int d) {
-    return FxOp{0, 0, fa + fb - f[d], w[d]};
+    return fx_op_finish(FxOp{0, 0, fa + fb - f[d], w[d], 0, 0, 0, 0, 0});
 }
 static FxOp add_op(const int* f, const int* w, int fa, int fb, int d) {
     const int fm = std::max(fa, fb);
-    return FxOp{fm - fa, fm - fb, fm - f[d], w[d]};
+    return fx_op_finish(FxOp{fm - fa, fm - fb, fm - f[d], w[d], 0, 0, 0, 0, 0});
 }
 
 // Method 1's MSE E[(Z - T_q[k(Z)])^2] = 1 - 2^-q sum_k T_q[k]^2 (T_q[k] is the mean
