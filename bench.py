@@ -681,10 +681,10 @@ def serving(M, ctx, costs, rates, seconds, warm=1.0, drain=30.0, max_active=256,
 
 def batch(M, ctx, costs, eps_list, n_opt=256, drivers=("engine",)):
     """The batched workload: n_opt options (draw_options with default_rng(1234)),
-    each to RMSE eps (normalised); nested vs plain FP32.  Wall time of
-    mlmc_estimate_batch, per sweep driver: 'engine' (run states on the device, one
-    graph replay per sweep of all options) or 'host' (each sweep planned on the host,
-    one launch sequence)."""
+    each to RMSE eps (normalised); nested vs plain FP32.  Wall time of the
+    mlmc_estimate_batch call (results converted to dicts after it), per sweep
+    driver: 'engine' (run states on the device, one graph replay per sweep of all
+    options) or 'host' (each sweep planned on the host, one launch sequence)."""
     import numpy as np
     rng = np.random.default_rng(1234)
     opts = draw_options(rng, n_opt)
@@ -704,8 +704,9 @@ def batch(M, ctx, costs, eps_list, n_opt=256, drivers=("engine",)):
             for mode in ("nested", "plain_fp32"):
                 cfg = _run_cfg(M, mode == "nested", eps, costs)
                 t0 = time.perf_counter()
-                rs = ctx.estimate_batch(probs, cfg, SEED)
+                raw = ctx.estimate_batch(probs, cfg, SEED, raw=True)
                 dt = time.perf_counter() - t0
+                rs = M.results_as_dicts(raw)
                 errs = [(r["estimate"] - closed_form(o)) / o["S0"] / eps for r, o in zip(rs, opts)
                         if closed_form(o) is not None]
                 ns = [sum(lv["n"][e] for lv in r["levels"] for e in range(3)) for r in rs]

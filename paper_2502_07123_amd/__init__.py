@@ -144,12 +144,14 @@ class Context:
                                   C.byref(r)), self.h)
         return r.as_dict()
 
-    def estimate_batch(self, problems, cfg, seed):
+    def estimate_batch(self, problems, cfg, seed, raw=False):
+        """One result dict per problem; raw: the mlmc_result array as returned (for
+        timing the call alone; results_as_dicts converts it)."""
         n = len(problems)
         arr = (Problem * n)(*problems)
         res = (Result * n)()
         check(lib().mlmc_estimate_batch(self.h, n, arr, C.byref(cfg), int(seed), res), self.h)
-        return [res[i].as_dict() for i in range(n)]
+        return res if raw else results_as_dicts(res)
 
     # ---- serving
     def server_start(self, run_cfg, max_active=256):
@@ -274,6 +276,11 @@ class SumsBatch:
 
 
 # ---------------------------------------------------------- host-side helpers
+def results_as_dicts(res):
+    """The dicts of an mlmc_result array."""
+    return [res[i].as_dict() for i in range(len(res))]
+
+
 def level_sums_static(problem, level, n_paths, path_offset, prec, estimator, seed, option=0,
                       out=None, stream=None):
     """mlmc_level_sums_static: the sums of one level into `out`, a device tensor of at

@@ -38,10 +38,15 @@ __host__ __device__ __forceinline__ MLMC_GLOBAL T* global_ptr(uint64_t addr) {
 // Stream positions of one path group: lcm(2^level, wpb), so that a group holds
 // whole paths and whole Philox blocks (wpb = 4 * indices per word).
 __host__ __device__ __forceinline__ uint64_t group_span(int level, uint32_t wpb) {
-    const uint64_t N = uint64_t(1) << level;
-    uint64_t a = N, b = wpb;
-    while (b) { const uint64_t t = a % b; a = b; b = t; }
-    return N / a * wpb;
+    // lcm(2^level, wpb) = wpb 2^(level - min(level, ctz(wpb)))
+    if (wpb == 0) return 0;
+    const int t = __builtin_ctz(wpb);
+    return uint64_t(wpb) << (level - (t < level ? t : level));
+}
+
+// a / b, in 32 bits when both fit (the same quotient, cheaper on the GPU)
+__host__ __device__ __forceinline__ uint64_t udiv_fast(uint64_t a, uint64_t b) {
+    return ((a | b) >> 32) == 0 ? uint64_t(uint32_t(a) / uint32_t(b)) : a / b;
 }
 
 // The tiles of one work: groups [g0, g1) (S stream positions each) in nt tiles of
@@ -58,17 +63,17 @@ __host__ __device__ inline WorkSplit split_groups(uint32_t tile_steps, uint32_t 
                                                   uint64_t max_tiles) {
     WorkSplit sp;
     const uint64_t G = S >> level;                             // paths per group
-    sp.g0 = path_begin / G;
-    sp.g1 = (path_begin + n - 1) / G + 1;
+    sp.g0 = udiv_fast(path_begin, G);
+    sp.g1 = udiv_fast(path_begin + n - 1, G) + 1;
     const uint64_t total = sp.g1 - sp.g0;
-    uint64_t ppt = tile_steps / (block * S);
+    uint64_t ppt = udiv_fast(tile_steps, uint64_t(block) * S);
     if (ppt < 1) ppt = 1;
-    const uint64_t fill = (total + uint64_t(block) * min_tiles - 1) / (uint64_t(block) * min_tiles);
+    const uint64_t fill = udiv_fast(total + uint64_t(block) * min_tiles - 1, uint64_t(block) * min_tiles);
     if (fill < ppt) ppt = fill;
     if (ppt < 1) ppt = 1;
     sp.per = uint64_t(block) * ppt;
-    if ((total + sp.per - 1) / sp.per > max_tiles) sp.per = (total + max_tiles - 1) / max_tiles;
-    sp.nt = (total + sp.per - 1) / sp.per;
+    if (udiv_fast(total + sp.per - 1, sp.per) > max_tiles) sp.per = udiv_fast(total + max_tiles - 1, max_tiles);
+    sp.nt = udiv_fast(total + sp.per - 1, sp.per);
     return sp;
 }
 

@@ -166,19 +166,20 @@ __host__ __device__ inline void run_advance(RunState& o) {
     }
     const double eps = o.eps;
     double lam = 0.0;
+    double Vs[RUN_LEVELS][2];                                   // the clamped variances, once
     for (int l = 0; l <= o.L; ++l)
         for (int i = 0; i < run_n_est(o, l); ++i) {
             const int e = run_est_at(o, l, i);
             double V = est_var(o.sums[l][e]);
             V = V < 1e-300 ? 1e-300 : V;
+            Vs[l][i] = V;
             lam += sqrt(V * o.cost[e] * ldexp(1.0, l));
         }
     lam /= o.theta * eps * eps;
     for (int l = 0; l <= o.L; ++l)
         for (int i = 0; i < run_n_est(o, l); ++i) {
             const int e = run_est_at(o, l, i);
-            double V = est_var(o.sums[l][e]);
-            V = V < 1e-300 ? 1e-300 : V;
+            const double V = Vs[l][i];
             const double target = ceil(lam * sqrt(V / (o.cost[e] * ldexp(1.0, l))));
             const uint64_t t = target > 1.8e19 ? UINT64_MAX : static_cast<uint64_t>(target);
             if (t > o.sums[l][e].n) run_push(o, l, e, t - o.sums[l][e].n);

@@ -5,7 +5,7 @@
 // -- and the driver's decisions), its prepared levels (constants and step tables)
 // and their launch classes.  One sweep is a fixed sequence of kernels, captured once
 // in a HIP graph and replayed:
-//   k_eng_advance  one thread per slot: the driver's next works (device/advance.hpp:
+//   k_eng_advance  one block per slot: the driver's next works (device/advance.hpp:
 //                  pilot, per-level estimator, optimal allocation, bias test);
 //   k_eng_plan     one block: the works of all slots into per-class work lists and
 //                  tile descriptors (the same tile split as a host-planned launch),
@@ -78,11 +78,14 @@ struct EngReduce {
 // per-slot planning scratch of k_eng_plan: each pending work's place in its class's
 // work list and its first tile there
 struct EngPlanScratch {
-    uint64_t total_tiles;
+    uint64_t total_tiles;         // the run's pending works' tiles
     uint32_t planned;
+    int32_t need;                 // highest level of a pending work not prepared yet (-1: none)
+    uint32_t bad;                 // a pending work's level has no launch class
     uint32_t pad;
     uint32_t iw[RUN_MAX_PEND];
     uint32_t t0[RUN_MAX_PEND];
+    WorkSplit sp[RUN_MAX_PEND];   // each pending work's tile split (computed once per sweep)
 };
 
 // device addresses of an engine's arrays (kernel arguments)
@@ -101,16 +104,31 @@ struct EngPtrs {
 
 // one contiguous piece of a host-to-device upload (engine_kernels k_scatter)
 struct EngSeg {
-    uint64_t src;               // byte offset in the staging buffer (multiple of 8)
+    uint64_t src;               // byte offset in the staging area (multiple of 8), or ENG_SEG_ZERO
     uint64_t dst;               // device address (multiple of 8)
     uint64_t bytes;             // multiple of 8
 };
+constexpr uint64_t ENG_SEG_ZERO = ~uint64_t(0);   // the segment's bytes are zeros
 
+// A step table built on the device: the (Z~_k, s_k) pairs of one (slot, level)'s
+// FP32 or FP16 table side, Z~_k from the engine's base table of the precision's
+// (q, method) and s_k the fine step's multiplier with that level's constants -- the
+// same operations as the host's table build (device/paths.hpp multiplier_lp).
+struct EngTableJob {
+    uint32_t lvl;               // LevelDev index [slot][level][estimator]
+    uint32_t table_off;         // destination, bytes into the table arena
+    uint32_t base_off;          // Z~ values, bytes into the base table area
+    uint16_t arith;             // MLMC_ARITH_FP32 or MLMC_ARITH_FP16
+    uint16_t mil;               // Milstein multiplier
+};
+
+hipError_t launch_eng_tables(const EngTableJob* jobs, uint32_t n, const LevelDev* levels, const uint8_t* base,
+                             uint8_t* tables, hipStream_t st);
 hipError_t launch_eng_advance(const EngPtrs& p, uint32_t n_slots, hipStream_t st);
 hipError_t launch_eng_plan(const EngPtrs& p, hipStream_t st);
 hipError_t launch_eng_reduce(const EngPtrs& p, uint32_t grid, hipStream_t st);
-// copies n segments from coherent pinned host memory (staging + segs, both host
-// buffers mapped into the device's address space) to device memory
+// copies n segments from a device staging area (staging + segs, device memory) to
+// their destinations
 hipError_t launch_eng_scatter(const uint8_t* staging, const EngSeg* segs, uint32_t n, hipStream_t st);
 
 }  // namespace mlmc

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 #include <string>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "engine.hpp"
@@ -57,28 +59,51 @@ struct Engine {
         size_t bytes = 0;
         hipEvent_t ev = nullptr;
     };
-    std::vector<StageBuf> stage;
-    // An upload: segments copied by one scatter launch, concurrently -- no two
+    std::vector<StageBuf> stage;                  // pinned host staging buffers
+    uint8_t* dstage = nullptr;                    // device staging area (workspace)
+    size_t dstage_bytes = 0;
+    // base tables (Z~ values per (arith, q, method) of the runs' FP32 / FP16 table
+    // sides) for the step tables built on the device, and their job list
+    std::vector<uint8_t> base_h;
+    std::vector<std::pair<std::tuple<int, int, int>, uint32_t>> base_index;   // key -> byte offset
+    uint8_t* base = nullptr;
+    EngTableJob* jobs = nullptr;
+    uint32_t jobs_cap = 0;
+    // An upload: segments copied by scatter launches, concurrently -- no two
     // segments of one upload may overlap.
     struct Upload {
         std::vector<uint8_t> data;
         std::vector<EngSeg> segs;
+        std::vector<EngTableJob> jobs;            // step tables the device builds after the copies
         uint8_t* put(const void* src, size_t bytes, uint64_t dst);
+        void zero(size_t bytes, uint64_t dst);    // bytes: multiple of 8
+    };
+    // levels [from, to) of the run in slot s
+    struct LevelTask {
+        uint32_t s;
+        const mlmc_problem* prob;
+        bool nested;
+        uint32_t from, to;
     };
 
     ~Engine();
     static size_t slot_bytes(uint32_t LV, size_t tstride);
+    mlmc_status build_bases();
+    bool base_of(int arith, int q, int method, uint32_t& off) const;
     mlmc_status create(mlmc_context* c, const mlmc_run_config& rc, const std::vector<EngKind>& k, uint32_t n);
     mlmc_status layout();
     mlmc_status capture(int k);
     mlmc_status flush(Upload& u);
     void stage_reset(Upload& u);
-    mlmc_status stage_levels(Upload& u, uint32_t s, const mlmc_problem& prob, bool nested, uint32_t from,
-                             uint32_t to);
+    // the levels of every task, prepared on up to 8 host threads, then staged in order
+    mlmc_status stage_tasks(Upload& u, const std::vector<LevelTask>& tasks);
+    // With `defer`, the run's (or its more) levels are appended there for one
+    // stage_tasks call over many runs; without, staged at once.
     mlmc_status stage_run(Upload& u, uint32_t s, const mlmc_problem& prob, const mlmc_run_config& rc,
-                          uint64_t seed, uint32_t option, bool put_meta);
+                          uint64_t seed, uint32_t option, bool put_meta, std::vector<LevelTask>* defer = nullptr);
     void stage_meta_all(Upload& u);
-    mlmc_status stage_more_levels(Upload& u, uint32_t s, const mlmc_problem& prob, bool nested, uint32_t need);
+    mlmc_status stage_more_levels(Upload& u, uint32_t s, const mlmc_problem& prob, bool nested, uint32_t need,
+                                  std::vector<LevelTask>* defer = nullptr);
     void stage_levels_ready(Upload& u, uint32_t s, uint32_t c3);
     mlmc_status replay(int k);
 };

@@ -7,23 +7,42 @@
 
 #include "device/advance.hpp"
 #include "device/philox.hpp"
+#include "device/paths.hpp"
 #include "device/reduce.hpp"
 #include "engine.hpp"
 
 namespace mlmc {
 
-// One thread per slot: a run whose previous works have all been added gets its next
+// One block per slot: a run whose previous works have all been added gets its next
 // works (or finishes).  Runs still holding works (not planned: a level not prepared
-// yet, or no tile capacity) keep them.
-__global__ void __launch_bounds__(64) k_eng_advance(EngPtrs p, uint32_t n_slots) {
-    const uint32_t s = blockIdx.x * 64u + threadIdx.x;
+// yet, or no tile capacity) keep them.  The state is staged in LDS by the block
+// (coalesced), the decisions run on one lane against LDS, and the state goes back.
+constexpr uint32_t ADV_THREADS = 64;
+static_assert(sizeof(RunState) % 8 == 0, "the state moves as 8-byte words");
+
+__global__ void __launch_bounds__(ADV_THREADS) k_eng_advance(EngPtrs p, uint32_t n_slots) {
+    __shared__ RunState o;
+    __shared__ uint32_t go;
+    const uint32_t s = blockIdx.x, tid = threadIdx.x;
     if (s >= n_slots) return;
-    EngMeta& m = p.meta[s];
-    if (!m.active || m.pending_valid) return;
-    RunState& o = p.states[s];
-    if (o.done) return;
-    run_advance(o);
-    m.pending_valid = o.n_pend > 0 ? 1u : 0u;
+    if (tid == 0) {
+        const EngMeta& m = p.meta[s];
+        go = (m.active && !m.pending_valid && !p.states[s].done) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!go) return;
+    constexpr uint32_t NW = sizeof(RunState) / 8;
+    const uint64_t* g = reinterpret_cast<const uint64_t*>(p.states + s);
+    uint64_t* l = reinterpret_cast<uint64_t*>(&o);
+    for (uint32_t k = tid; k < NW; k += ADV_THREADS) l[k] = g[k];
+    __syncthreads();
+    if (tid == 0) {
+        run_advance(o);
+        p.meta[s].pending_valid = o.n_pend > 0 ? 1u : 0u;
+    }
+    __syncthreads();
+    uint64_t* gw = reinterpret_cast<uint64_t*>(p.states + s);
+    for (uint32_t k = tid; k < NW; k += ADV_THREADS) gw[k] = l[k];
 }
 
 __device__ __forceinline__ WorkSplit eng_split(const EngHeader& H, const EngLevelInfo& in, int level,
@@ -34,23 +53,27 @@ __device__ __forceinline__ WorkSplit eng_split(const EngHeader& H, const EngLeve
 
 constexpr uint32_t PLAN_THREADS = 1024;
 
-// One block: the pending works of every run into per-class work lists.
-//  1. per slot: are its works' levels prepared, its tiles in all; a prefix sum of
-//     the tiles over the slots (in slot order) keeps the runs that fit the tile
-//     slots (the rest wait for a later sweep);
-//  2. per planned work: its place in its class's list and its first tile there, one
+// One block: the pending works of every run into per-class work lists.  Phases over
+// (slot, pending work) pairs run on all threads; phases over slots one thread per slot.
+//  A. per slot: clear its aggregates;
+//  B. per work: a level not prepared yet raises the slot's wait level; else the
+//     work's tile split, its tiles added into the slot's total;
+//  C. per slot: status; a prefix sum of the tiles over the slots (in slot order)
+//     keeps the runs that fit the tile slots (the rest wait for a later sweep);
+//  D. per planned work: its place in its class's list and its first tile there, one
 //     64-bit LDS atomic per work (place and tiles from one add, so the tile ranges
 //     follow the places and the path kernels' tile search stays valid);
-//  3. class offsets and counts (the path kernels read these);
-//  4. per slot: work descriptors, tile descriptors and reduction entries, path
-//     ranges continuing at the run's sample counts;
-//  5. status words for the host.
+//  E. class offsets and counts (the path kernels read these);
+//  F. per planned work: work descriptor, tile descriptor and reduction entry, the
+//     path range continuing at the run's sample count;
+//  G. per slot: the works handed over; status words for the host.
 // The order of works within a class may change from replay to replay; no result
 // depends on it (a work's sums depend on its own tiles only, and a run adds at most
 // one work per (level, estimator) per sweep).
 __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
     EngHeader& H = *p.hdr;
     const uint32_t C = H.n_slots, LV = H.n_levels, NC = H.n_classes;
+    const uint32_t NI = C * static_cast<uint32_t>(RUN_MAX_PEND);
     const uint32_t tid = threadIdx.x;
     __shared__ unsigned long long cls_acc[ENG_MAX_CLASSES];   // works << 32 | tiles
     __shared__ uint64_t scan[PLAN_THREADS];
@@ -61,36 +84,59 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
         carry = 0;
         n_planned = n_deferred = 0;
     }
+    // A
+    for (uint32_t s = tid; s < C; s += PLAN_THREADS) {
+        EngPlanScratch& sc = p.scratch[s];
+        sc.total_tiles = 0;
+        sc.need = -1;
+        sc.bad = 0;
+    }
     __syncthreads();
+    // B
+    for (uint32_t idx = tid; idx < NI; idx += PLAN_THREADS) {
+        const uint32_t s = idx / static_cast<uint32_t>(RUN_MAX_PEND);
+        const int j = static_cast<int>(idx % static_cast<uint32_t>(RUN_MAX_PEND));
+        const EngMeta& m = p.meta[s];
+        if (!m.active || !m.pending_valid) continue;
+        const RunState& o = p.states[s];
+        if (j >= o.n_pend) continue;
+        EngPlanScratch& sc = p.scratch[s];
+        const int l = o.pend[j].level, e = o.pend[j].est;
+        if (l >= static_cast<int>(m.levels_ready)) {
+            atomicMax(&sc.need, l);
+            continue;
+        }
+        const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
+        if (in.cls >= NC || in.block == 0 || in.wpb == 0) {
+            atomicOr(&sc.bad, 1u);
+            continue;
+        }
+        const WorkSplit sp = eng_split(H, in, l, o.sums[l][e].n, o.pend[j].n);
+        sc.sp[j] = sp;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&sc.total_tiles), static_cast<unsigned long long>(sp.nt));
+    }
+    __syncthreads();
+    // C
     for (uint32_t base = 0; base < C; base += PLAN_THREADS) {
         const uint32_t s = base + tid;
         uint64_t total = 0;
         uint32_t planned = 0;
         if (s < C) {
             EngMeta& m = p.meta[s];
+            EngPlanScratch& sc = p.scratch[s];
             uint32_t status = 0;
             if (m.active) {
-                const RunState& o = p.states[s];
-                if (o.done) status |= ENG_DONE;
+                if (p.states[s].done) status |= ENG_DONE;
                 if (m.pending_valid) {
-                    int need = -1;
-                    for (int j = 0; j < o.n_pend; ++j)
-                        if (o.pend[j].level >= static_cast<int>(m.levels_ready) && o.pend[j].level > need)
-                            need = o.pend[j].level;
+                    const int need = __hip_atomic_load(&sc.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t bad = __hip_atomic_load(&sc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (need >= 0) {
                         status |= ENG_WAIT_LEVEL | (static_cast<uint32_t>(need) << 8);
+                    } else if (bad) {
+                        H.error = 2u;                                      // never planned
                     } else {
                         planned = 1;
-                        for (int j = 0; j < o.n_pend; ++j) {
-                            const int l = o.pend[j].level, e = o.pend[j].est;
-                            const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
-                            if (in.cls >= NC || in.block == 0 || in.wpb == 0) {   // never planned
-                                H.error = 2u;
-                                planned = 0;
-                                break;
-                            }
-                            total += eng_split(H, in, l, o.sums[l][e].n, o.pend[j].n).nt;
-                        }
+                        total = __hip_atomic_load(&sc.total_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
@@ -110,28 +156,27 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
             atomicAdd(&n_deferred, 1u);
         }
         if (planned) atomicAdd(&n_planned, 1u);
-        if (s < C) {
-            p.scratch[s].planned = planned;
-            p.scratch[s].total_tiles = total;
-        }
+        if (s < C) p.scratch[s].planned = planned;
         __syncthreads();
         if (tid == PLAN_THREADS - 1) carry += scan[tid];
         __syncthreads();
     }
-    for (uint32_t s = tid; s < C; s += PLAN_THREADS) {
+    // D
+    for (uint32_t idx = tid; idx < NI; idx += PLAN_THREADS) {
+        const uint32_t s = idx / static_cast<uint32_t>(RUN_MAX_PEND);
+        const int j = static_cast<int>(idx % static_cast<uint32_t>(RUN_MAX_PEND));
         EngPlanScratch& sc = p.scratch[s];
         if (!sc.planned) continue;
         const RunState& o = p.states[s];
-        for (int j = 0; j < o.n_pend; ++j) {
-            const int l = o.pend[j].level, e = o.pend[j].est;
-            const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
-            const uint64_t nt = eng_split(H, in, l, o.sums[l][e].n, o.pend[j].n).nt;
-            const unsigned long long old = atomicAdd(&cls_acc[in.cls], (1ull << 32) | nt);
-            sc.iw[j] = static_cast<uint32_t>(old >> 32);
-            sc.t0[j] = static_cast<uint32_t>(old & 0xFFFFFFFFull);
-        }
+        if (j >= o.n_pend) continue;
+        const int l = o.pend[j].level, e = o.pend[j].est;
+        const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
+        const unsigned long long old = atomicAdd(&cls_acc[in.cls], (1ull << 32) | sc.sp[j].nt);
+        sc.iw[j] = static_cast<uint32_t>(old >> 32);
+        sc.t0[j] = static_cast<uint32_t>(old & 0xFFFFFFFFull);
     }
     __syncthreads();
+    // E
     if (tid == 0) {
         uint32_t ow = 0, ot = 0;
         for (uint32_t c = 0; c < NC; ++c) {
@@ -151,58 +196,64 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
         H.deferred = n_deferred;
     }
     __syncthreads();
-    for (uint32_t s = tid; s < C; s += PLAN_THREADS) {
-        EngPlanScratch& sc = p.scratch[s];
+    // F
+    for (uint32_t idx = tid; idx < NI; idx += PLAN_THREADS) {
+        const uint32_t s = idx / static_cast<uint32_t>(RUN_MAX_PEND);
+        const int j = static_cast<int>(idx % static_cast<uint32_t>(RUN_MAX_PEND));
+        const EngPlanScratch& sc = p.scratch[s];
         if (!sc.planned) continue;
-        RunState& o = p.states[s];
-        EngMeta& m = p.meta[s];
-        for (int j = 0; j < o.n_pend; ++j) {
-            const int l = o.pend[j].level, e = o.pend[j].est;
-            const uint64_t n = o.pend[j].n;
-            const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
-            const uint32_t c = in.cls;
-            const uint64_t begin = o.sums[l][e].n;
-            const WorkSplit sp = eng_split(H, in, l, begin, n);
-            const uint32_t gw = H.class_work_off[c] + sc.iw[j];
-            const uint32_t t0 = sc.t0[j];
-            WorkDev W;
-            W.lvl = (s * LV + static_cast<uint32_t>(l)) * 3u + static_cast<uint32_t>(e);
-            W.c2 = stream_c2(l, e);
-            W.c3 = m.c3;
-            W.k0 = m.k0;
-            W.k1 = m.k1;
-            W.pad0 = 0;
-            W.path_begin = begin;
-            W.path_end = begin + n;
-            W.debug = 0;
-            W.zbuf = 0;
-            W.jbuf = 0;
-            p.works[gw] = W;
-            WorkTilesDev wt;
-            wt.g0 = sp.g0;
-            wt.g1 = sp.g1;
-            wt.per = sp.per;
-            wt.work = gw;
-            wt.tile_end = t0 + static_cast<uint32_t>(sp.nt);
-            wt.slot_begin = H.class_slot_off[c] + t0;
-            wt.pad = 0;
-            p.wtiles[gw] = wt;
-            EngReduce rd;
-            rd.slot_begin = wt.slot_begin;
-            rd.slot_end = wt.slot_begin + static_cast<uint32_t>(sp.nt);
-            rd.kind = in.kind;
-            rd.run = s;
-            rd.level = l;
-            rd.est = e;
-            rd.n = n;
-            p.red[gw] = rd;
-        }
-        m.pending_valid = 0;
-        o.sweeps += 1;
+        const RunState& o = p.states[s];
+        if (j >= o.n_pend) continue;
+        const EngMeta& m = p.meta[s];
+        const int l = o.pend[j].level, e = o.pend[j].est;
+        const uint64_t n = o.pend[j].n;
+        const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
+        const uint32_t c = in.cls;
+        const uint64_t begin = o.sums[l][e].n;
+        const WorkSplit sp = sc.sp[j];
+        const uint32_t gw = H.class_work_off[c] + sc.iw[j];
+        const uint32_t t0 = sc.t0[j];
+        WorkDev W;
+        W.lvl = (s * LV + static_cast<uint32_t>(l)) * 3u + static_cast<uint32_t>(e);
+        W.c2 = stream_c2(l, e);
+        W.c3 = m.c3;
+        W.k0 = m.k0;
+        W.k1 = m.k1;
+        W.pad0 = 0;
+        W.path_begin = begin;
+        W.path_end = begin + n;
+        W.debug = 0;
+        W.zbuf = 0;
+        W.jbuf = 0;
+        p.works[gw] = W;
+        WorkTilesDev wt;
+        wt.g0 = sp.g0;
+        wt.g1 = sp.g1;
+        wt.per = sp.per;
+        wt.work = gw;
+        wt.tile_end = t0 + static_cast<uint32_t>(sp.nt);
+        wt.slot_begin = H.class_slot_off[c] + t0;
+        wt.pad = 0;
+        p.wtiles[gw] = wt;
+        EngReduce rd;
+        rd.slot_begin = wt.slot_begin;
+        rd.slot_end = wt.slot_begin + static_cast<uint32_t>(sp.nt);
+        rd.kind = in.kind;
+        rd.run = s;
+        rd.level = l;
+        rd.est = e;
+        rd.n = n;
+        p.red[gw] = rd;
     }
     __syncthreads();
-    for (uint32_t s = tid; s < C; s += PLAN_THREADS)
+    // G
+    for (uint32_t s = tid; s < C; s += PLAN_THREADS) {
+        if (p.scratch[s].planned) {
+            p.meta[s].pending_valid = 0;
+            p.states[s].sweeps += 1;
+        }
         p.status_out[s] = (p.meta[s].status & 0xFFFFu) | (p.meta[s].generation << 16);
+    }
     if (tid == 0) p.status_out[C] = H.error;
 }
 
@@ -244,24 +295,60 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_eng_reduce(EngPtrs p) {
     }
 }
 
-// Uploads: block b copies segments b, b + grid, ... (system-scope loads: the staging
-// buffer and the segment list are coherent pinned host memory).
+// Uploads: block b copies segments b, b + grid, ... from the device staging area
+// (filled by a DMA copy from pinned host memory) or writes zeros.
 __global__ void __launch_bounds__(256) k_eng_scatter(const uint8_t* __restrict__ staging,
                                                      const EngSeg* __restrict__ segs, uint32_t n) {
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const uint64_t* sp = reinterpret_cast<const uint64_t*>(segs + i);
-        const uint64_t src = __hip_atomic_load(sp + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint64_t dst = __hip_atomic_load(sp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint64_t bytes = __hip_atomic_load(sp + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint64_t* s = reinterpret_cast<const uint64_t*>(staging + src);
-        uint64_t* d = reinterpret_cast<uint64_t*>(dst);
-        for (uint64_t k = threadIdx.x; k < bytes / 8; k += 256)
-            d[k] = __hip_atomic_load(s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const EngSeg g = segs[i];
+        uint64_t* d = reinterpret_cast<uint64_t*>(g.dst);
+        const uint64_t nw = g.bytes / 8;
+        if (g.src == ENG_SEG_ZERO) {
+            for (uint64_t k = threadIdx.x; k < nw; k += 256) d[k] = 0;
+        } else {
+            const uint64_t* s = reinterpret_cast<const uint64_t*>(staging + g.src);
+            for (uint64_t k = threadIdx.x; k < nw; k += 256) d[k] = s[k];
+        }
     }
 }
 
+// One block per job; entries k = tid, tid + 256, ... of the level's 2^q.
+__global__ void __launch_bounds__(256) k_eng_tables(const EngTableJob* __restrict__ jobs, const LevelDev* levels,
+                                                    const uint8_t* __restrict__ base, uint8_t* tables) {
+    const EngTableJob j = jobs[blockIdx.x];
+    const LevelDev& L = levels[j.lvl];
+    const uint32_t n = L.table_entries;
+    if (j.arith == MLMC_ARITH_FP32) {
+        const float* z = reinterpret_cast<const float*>(base + j.base_off);
+        float* t = reinterpret_cast<float*>(tables + j.table_off);
+        for (uint32_t k = threadIdx.x; k < n; k += 256) {
+            const float zk = z[k];
+            t[2 * k] = zk;
+            t[2 * k + 1] = j.mil ? multiplier32<true>(zk, L.fcon1, L.fcon2, L.fcon3, 1.0f)
+                                 : multiplier32<false>(zk, L.fcon1, L.fcon2, L.fcon3, 1.0f);
+        }
+    } else {
+        const _Float16* z = reinterpret_cast<const _Float16*>(base + j.base_off);
+        _Float16* t = reinterpret_cast<_Float16*>(tables + j.table_off);
+        const _Float16 one = 1;
+        for (uint32_t k = threadIdx.x; k < n; k += 256) {
+            const _Float16 zk = z[k];
+            t[2 * k] = zk;
+            t[2 * k + 1] = j.mil ? multiplier_lp<true, _Float16>(zk, L.hcon1, L.hcon2, L.hcon3, one)
+                                 : multiplier_lp<false, _Float16>(zk, L.hcon1, L.hcon2, L.hcon3, one);
+        }
+    }
+}
+
+hipError_t launch_eng_tables(const EngTableJob* jobs, uint32_t n, const LevelDev* levels, const uint8_t* base,
+                             uint8_t* tables, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eng_tables, dim3(n), dim3(256), 0, st, jobs, levels, base, tables);
+    return hipGetLastError();
+}
+
 hipError_t launch_eng_advance(const EngPtrs& p, uint32_t n_slots, hipStream_t st) {
-    hipLaunchKernelGGL(k_eng_advance, dim3((n_slots + 63) / 64), dim3(64), 0, st, p, n_slots);
+    hipLaunchKernelGGL(k_eng_advance, dim3(n_slots), dim3(ADV_THREADS), 0, st, p, n_slots);
     return hipGetLastError();
 }
 

@@ -456,7 +456,7 @@ static const std::vector<float>& table_values_f32(int q, int method) {
 }
 
 mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_precision* prec,
-                          int32_t estimator, LevelPrep& out, std::string& err) {
+                          int32_t estimator, LevelPrep& out, std::string& err, bool with_table) {
     LevelDev& L = out.dev;
     std::memset(&L, 0, sizeof(L));
     const bool mil = p->scheme == MLMC_MILSTEIN;
@@ -506,16 +506,51 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
     const MethodTable* mt = method == 1 ? nullptr : &method_table(q, method);
     // the values to tabulate, Method 1's exact interval means or Methods 2 / 3 in FP64
     // (the FP32 side takes them rounded once, from a per-(q, method) cache)
-    std::vector<long double> T;
-    if (prec->arith != MLMC_ARITH_FP32) {
+    std::vector<long double> Tm;
+    const std::vector<long double>* Tp = nullptr;
+    if (prec->arith != MLMC_ARITH_FP32 && with_table) {
         if (method == 1) {
-            T = method1_table(q);
+            Tp = &method1_table(q);
         } else {
-            T.resize(n);
-            for (uint32_t k = 0; k < n; ++k) T[k] = mt->z[k];
+            Tm.resize(n);
+            for (uint32_t k = 0; k < n; ++k) Tm[k] = mt->z[k];
+            Tp = &Tm;
         }
     }
+    const std::vector<long double>& T = Tp ? *Tp : Tm;
     L.table_entries = n;
+    const bool needs_perm = mt && !mt->perm.empty() && estimator == MLMC_EST_CORR;
+    if (!with_table && !needs_perm) {
+        // the caller shares the bytes of an identical table (same arithmetic, q and
+        // method); the constants are still this level's
+        const size_t entry = prec->arith == MLMC_ARITH_FP16 ? 4 : 8;
+        if (prec->arith == MLMC_ARITH_FIXED) {
+            const int* f = prec->frac_bits;
+            const int* w = prec->word_bits;
+            L.fX = f[MLMC_V_X];
+            L.wX = w[MLMC_V_X];
+            L.icon1 = quantize_double(L.con1, f[MLMC_V_CON1], w[MLMC_V_CON1]);
+            L.icon1c = quantize_double(L.con1c, f[MLMC_V_CON1], w[MLMC_V_CON1]);
+            L.icon2 = quantize_double(L.con2, f[MLMC_V_CON2], w[MLMC_V_CON2]);
+            L.icon3 = mil ? quantize_double(L.con3, f[MLMC_V_CON3], w[MLMC_V_CON3]) : 0;
+            L.ik = quantize_double(L.k, f[MLMC_V_X], w[MLMC_V_X]);
+            L.ib = quantize_double(L.b, f[MLMC_V_X], w[MLMC_V_X]);
+            const int S = mil ? MLMC_V_SUM2 : MLMC_V_SUM1;
+            L.op_mul2 = mul_op(f, w, MLMC_V_X, S, MLMC_V_MUL2);
+            L.op_addX = add_op(f, w, f[MLMC_V_X], f[MLMC_V_MUL2], MLMC_V_X);
+            L.op_mul1 = mul_op(f, w, MLMC_V_CON2, MLMC_V_Z, MLMC_V_MUL1);
+            L.op_sum1 = add_op(f, w, f[MLMC_V_CON1], f[MLMC_V_MUL1], MLMC_V_SUM1);
+            if (mil) {
+                L.op_zsq = mul_op_fz(f, w, f[MLMC_V_Z], f[MLMC_V_Z], MLMC_V_ZSQ);
+                L.op_zm1 = add_op(f, w, f[MLMC_V_ZSQ], f[MLMC_V_ZSQ], MLMC_V_ZM1);
+                L.op_mul3 = mul_op(f, w, MLMC_V_CON3, MLMC_V_ZM1, MLMC_V_MUL3);
+                L.op_sum2 = add_op(f, w, f[MLMC_V_SUM1], f[MLMC_V_MUL3], MLMC_V_SUM2);
+                L.izm_c2 = int64_t(2) << f[MLMC_V_ZSQ];
+            }
+        }
+        L.table_bytes = static_cast<uint32_t>((n * entry + 15) & ~size_t(15));
+        return MLMC_OK;
+    }
     if (prec->arith == MLMC_ARITH_FP32) {
         // (Z~_k, s_k): s_k is the fine step's multiplier of Z~_k, formed with the
         // same FP32 operations the kernels use on the coarse path
@@ -589,7 +624,7 @@ mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_preci
         }
     }
     // Method 2's permutation for the exact side of the correction estimator
-    if (mt && !mt->perm.empty() && estimator == MLMC_EST_CORR) {
+    if (needs_perm) {
         const size_t off = (out.table.size() + 15) & ~size_t(15);
         out.table.resize(off + 2 * static_cast<size_t>(n), 0);
         std::memcpy(&out.table[off], mt->perm.data(), 2 * static_cast<size_t>(n));

@@ -42,8 +42,11 @@ struct LevelPrep {
 
 // Builds constants, the step table and the variant.  MLMC_E_OVERFLOW when a
 // fixed-point table entry saturates (the table-driven part must be exact).
+// with_table false: no table bytes (table_bytes still set) unless the estimator's
+// table differs from the approximate estimator's of the same precision (Method 2's
+// correction table carries the permutation) -- for callers that share that table.
 mlmc_status prepare_level(const mlmc_problem* p, int32_t level, const mlmc_precision* prec,
-                          int32_t estimator, LevelPrep& out, std::string& err);
+                          int32_t estimator, LevelPrep& out, std::string& err, bool with_table = true);
 
 int popcount32(uint32_t v);
 

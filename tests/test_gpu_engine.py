@@ -112,3 +112,20 @@ def test_engine_small_workspace_falls_back():
         r1 = small.estimate(prob, cfg, SEED)
         r2 = big.estimate(prob, cfg, SEED)
         _same(r1, r2, "single")
+
+
+def test_engine_reused_after_another_engine(ctx):
+    """Engines of one context share its workspace: a cached engine used again after
+    another one ran (here a plain run's engine, then the nested run's again, FP32 and
+    FP16 tables built on the device) gives the host-driven result."""
+    prob = M.make_problem("milstein", ("euro",), **EURO)
+    for arith in ("fp32", "fp16"):
+        nested, plain = _cfg(True, arith=arith, packed=True), _cfg(False)
+        ctx.set_driver(False)
+        ref = ctx.estimate(prob, nested, SEED, option=3)
+        ctx.set_driver(True)
+        first = ctx.estimate(prob, nested, SEED, option=3)
+        ctx.estimate(prob, plain, SEED, option=4)
+        again = ctx.estimate(prob, nested, SEED, option=3)
+        _same(ref, first, arith)
+        _same(ref, again, arith + " after another engine")
