@@ -75,17 +75,24 @@ struct EngReduce {
     uint64_t n;
 };
 
-// per-slot planning scratch of k_eng_plan: each pending work's place in its class's
-// work list and its first tile there
+// one pending work of a run as the sweep plans it (written by k_eng_advance, read by
+// k_eng_plan)
+struct EngWorkPlan {
+    WorkSplit sp;                 // its tile split
+    uint64_t begin, n;            // path range [begin, begin + n) of its stream
+    int32_t level, est;
+    uint32_t cls, kind;           // launch class, reduction kind
+    uint32_t iw, t0;              // its place in its class's list and its first tile there
+};
+
+// per-slot planning scratch
 struct EngPlanScratch {
     uint64_t total_tiles;         // the run's pending works' tiles
     uint32_t planned;
     int32_t need;                 // highest level of a pending work not prepared yet (-1: none)
     uint32_t bad;                 // a pending work's level has no launch class
-    uint32_t pad;
-    uint32_t iw[RUN_MAX_PEND];
-    uint32_t t0[RUN_MAX_PEND];
-    WorkSplit sp[RUN_MAX_PEND];   // each pending work's tile split (computed once per sweep)
+    uint32_t n_works;
+    EngWorkPlan w[RUN_MAX_PEND];
 };
 
 // device addresses of an engine's arrays (kernel arguments)

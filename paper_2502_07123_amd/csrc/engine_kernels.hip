@@ -13,21 +13,36 @@
 
 namespace mlmc {
 
-// One block per slot: a run whose previous works have all been added gets its next
-// works (or finishes).  Runs still holding works (not planned: a level not prepared
-// yet, or no tile capacity) keep them.  The state is staged in LDS by the block
-// (coalesced), the decisions run on one lane against LDS, and the state goes back.
+__device__ __forceinline__ WorkSplit eng_split(const EngHeader& H, const EngLevelInfo& in, int level,
+                                               uint64_t begin, uint64_t n) {
+    return split_groups(H.tile_steps, H.min_tiles, in.block, group_span(level, in.wpb), level, begin, n,
+                        H.max_tiles_work);
+}
+
+// One block (one wave) per slot.  A run whose previous works have all been added
+// gets its next works (or finishes); runs still holding works (not planned: a level
+// not prepared yet, or no tile capacity) keep them.  The state is staged in LDS by
+// the block (coalesced) and the decisions run on one lane against LDS.  Then, lane j
+// per pending work j: its level's readiness, launch class and tile split into the
+// slot's planning scratch, with the slot's totals.
 constexpr uint32_t ADV_THREADS = 64;
 static_assert(sizeof(RunState) % 8 == 0, "the state moves as 8-byte words");
+static_assert(RUN_MAX_PEND <= ADV_THREADS, "one lane per pending work");
 
 __global__ void __launch_bounds__(ADV_THREADS) k_eng_advance(EngPtrs p, uint32_t n_slots) {
     __shared__ RunState o;
-    __shared__ uint32_t go;
+    __shared__ uint32_t go, pend;
+    __shared__ uint64_t nt_l[ADV_THREADS];
+    __shared__ int32_t need_l[ADV_THREADS];
+    __shared__ uint32_t bad_l[ADV_THREADS];
     const uint32_t s = blockIdx.x, tid = threadIdx.x;
     if (s >= n_slots) return;
+    const EngHeader& H = *p.hdr;
+    EngMeta& m = p.meta[s];
     if (tid == 0) {
-        const EngMeta& m = p.meta[s];
-        go = (m.active && !m.pending_valid && !p.states[s].done) ? 1u : 0u;
+        // 1: holds works, 2: may advance, 0: nothing to do (inactive or finished)
+        go = !m.active ? 0u : (m.pending_valid ? 1u : (p.states[s].done ? 0u : 2u));
+        pend = 0;
     }
     __syncthreads();
     if (!go) return;
@@ -36,36 +51,81 @@ __global__ void __launch_bounds__(ADV_THREADS) k_eng_advance(EngPtrs p, uint32_t
     uint64_t* l = reinterpret_cast<uint64_t*>(&o);
     for (uint32_t k = tid; k < NW; k += ADV_THREADS) l[k] = g[k];
     __syncthreads();
-    if (tid == 0) {
-        run_advance(o);
-        p.meta[s].pending_valid = o.n_pend > 0 ? 1u : 0u;
+    if (go == 2) {
+        if (tid == 0) {
+            run_advance(o);
+            m.pending_valid = o.n_pend > 0 ? 1u : 0u;
+            pend = o.n_pend > 0 ? 1u : 0u;
+        }
+        __syncthreads();
+        uint64_t* gw = reinterpret_cast<uint64_t*>(p.states + s);
+        for (uint32_t k = tid; k < NW; k += ADV_THREADS) gw[k] = l[k];
+    } else if (tid == 0) {
+        pend = 1;
     }
     __syncthreads();
-    uint64_t* gw = reinterpret_cast<uint64_t*>(p.states + s);
-    for (uint32_t k = tid; k < NW; k += ADV_THREADS) gw[k] = l[k];
-}
-
-__device__ __forceinline__ WorkSplit eng_split(const EngHeader& H, const EngLevelInfo& in, int level,
-                                               uint64_t begin, uint64_t n) {
-    return split_groups(H.tile_steps, H.min_tiles, in.block, group_span(level, in.wpb), level, begin, n,
-                        H.max_tiles_work);
+    if (!pend) return;
+    const uint32_t LV = H.n_levels, NC = H.n_classes;
+    const int j = static_cast<int>(tid);
+    uint64_t nt = 0;
+    int32_t need = -1;
+    uint32_t bad = 0;
+    if (j < o.n_pend) {
+        const int lv = o.pend[j].level, e = o.pend[j].est;
+        if (lv >= static_cast<int>(m.levels_ready)) {
+            need = lv;
+        } else {
+            const EngLevelInfo in = p.info[(s * LV + lv) * 3u + e];
+            if (in.cls >= NC || in.block == 0 || in.wpb == 0) {
+                bad = 1;
+            } else {
+                EngWorkPlan wp;
+                wp.begin = o.sums[lv][e].n;
+                wp.n = o.pend[j].n;
+                wp.sp = eng_split(H, in, lv, wp.begin, wp.n);
+                wp.level = lv;
+                wp.est = e;
+                wp.cls = in.cls;
+                wp.kind = in.kind;
+                wp.iw = wp.t0 = 0;
+                p.scratch[s].w[j] = wp;
+                nt = wp.sp.nt;
+            }
+        }
+    }
+    nt_l[tid] = nt;
+    need_l[tid] = need;
+    bad_l[tid] = bad;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t t = 0;
+        int32_t nd = -1;
+        uint32_t bd = 0;
+        for (uint32_t k = 0; k < ADV_THREADS; ++k) {
+            t += nt_l[k];
+            nd = need_l[k] > nd ? need_l[k] : nd;
+            bd |= bad_l[k];
+        }
+        EngPlanScratch& sc = p.scratch[s];
+        sc.total_tiles = t;
+        sc.need = nd;
+        sc.bad = bd;
+        sc.n_works = static_cast<uint32_t>(o.n_pend);
+    }
 }
 
 constexpr uint32_t PLAN_THREADS = 1024;
 
-// One block: the pending works of every run into per-class work lists.  Phases over
-// (slot, pending work) pairs run on all threads; phases over slots one thread per slot.
-//  A. per slot: clear its aggregates;
-//  B. per work: a level not prepared yet raises the slot's wait level; else the
-//     work's tile split, its tiles added into the slot's total;
+// One block: the pending works of every run into per-class work lists, from the
+// planning scratch k_eng_advance wrote.  Phases over (slot, pending work) pairs run
+// on all threads; phases over slots one thread per slot.
 //  C. per slot: status; a prefix sum of the tiles over the slots (in slot order)
 //     keeps the runs that fit the tile slots (the rest wait for a later sweep);
 //  D. per planned work: its place in its class's list and its first tile there, one
 //     64-bit LDS atomic per work (place and tiles from one add, so the tile ranges
 //     follow the places and the path kernels' tile search stays valid);
 //  E. class offsets and counts (the path kernels read these);
-//  F. per planned work: work descriptor, tile descriptor and reduction entry, the
-//     path range continuing at the run's sample count;
+//  F. per planned work: work descriptor, tile descriptor and reduction entry;
 //  G. per slot: the works handed over; status words for the host.
 // The order of works within a class may change from replay to replay; no result
 // depends on it (a work's sums depend on its own tiles only, and a run adds at most
@@ -84,37 +144,6 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
         carry = 0;
         n_planned = n_deferred = 0;
     }
-    // A
-    for (uint32_t s = tid; s < C; s += PLAN_THREADS) {
-        EngPlanScratch& sc = p.scratch[s];
-        sc.total_tiles = 0;
-        sc.need = -1;
-        sc.bad = 0;
-    }
-    __syncthreads();
-    // B
-    for (uint32_t idx = tid; idx < NI; idx += PLAN_THREADS) {
-        const uint32_t s = idx / static_cast<uint32_t>(RUN_MAX_PEND);
-        const int j = static_cast<int>(idx % static_cast<uint32_t>(RUN_MAX_PEND));
-        const EngMeta& m = p.meta[s];
-        if (!m.active || !m.pending_valid) continue;
-        const RunState& o = p.states[s];
-        if (j >= o.n_pend) continue;
-        EngPlanScratch& sc = p.scratch[s];
-        const int l = o.pend[j].level, e = o.pend[j].est;
-        if (l >= static_cast<int>(m.levels_ready)) {
-            atomicMax(&sc.need, l);
-            continue;
-        }
-        const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
-        if (in.cls >= NC || in.block == 0 || in.wpb == 0) {
-            atomicOr(&sc.bad, 1u);
-            continue;
-        }
-        const WorkSplit sp = eng_split(H, in, l, o.sums[l][e].n, o.pend[j].n);
-        sc.sp[j] = sp;
-        atomicAdd(reinterpret_cast<unsigned long long*>(&sc.total_tiles), static_cast<unsigned long long>(sp.nt));
-    }
     __syncthreads();
     // C
     for (uint32_t base = 0; base < C; base += PLAN_THREADS) {
@@ -123,20 +152,18 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
         uint32_t planned = 0;
         if (s < C) {
             EngMeta& m = p.meta[s];
-            EngPlanScratch& sc = p.scratch[s];
+            const EngPlanScratch& sc = p.scratch[s];
             uint32_t status = 0;
             if (m.active) {
                 if (p.states[s].done) status |= ENG_DONE;
                 if (m.pending_valid) {
-                    const int need = __hip_atomic_load(&sc.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const uint32_t bad = __hip_atomic_load(&sc.bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (need >= 0) {
-                        status |= ENG_WAIT_LEVEL | (static_cast<uint32_t>(need) << 8);
-                    } else if (bad) {
+                    if (sc.need >= 0) {
+                        status |= ENG_WAIT_LEVEL | (static_cast<uint32_t>(sc.need) << 8);
+                    } else if (sc.bad) {
                         H.error = 2u;                                      // never planned
                     } else {
                         planned = 1;
-                        total = __hip_atomic_load(&sc.total_tiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        total = sc.total_tiles;
                     }
                 }
             }
@@ -164,16 +191,13 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
     // D
     for (uint32_t idx = tid; idx < NI; idx += PLAN_THREADS) {
         const uint32_t s = idx / static_cast<uint32_t>(RUN_MAX_PEND);
-        const int j = static_cast<int>(idx % static_cast<uint32_t>(RUN_MAX_PEND));
+        const uint32_t j = idx % static_cast<uint32_t>(RUN_MAX_PEND);
         EngPlanScratch& sc = p.scratch[s];
-        if (!sc.planned) continue;
-        const RunState& o = p.states[s];
-        if (j >= o.n_pend) continue;
-        const int l = o.pend[j].level, e = o.pend[j].est;
-        const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
-        const unsigned long long old = atomicAdd(&cls_acc[in.cls], (1ull << 32) | sc.sp[j].nt);
-        sc.iw[j] = static_cast<uint32_t>(old >> 32);
-        sc.t0[j] = static_cast<uint32_t>(old & 0xFFFFFFFFull);
+        if (!sc.planned || j >= sc.n_works) continue;
+        EngWorkPlan& w = sc.w[j];
+        const unsigned long long old = atomicAdd(&cls_acc[w.cls], (1ull << 32) | w.sp.nt);
+        w.iw = static_cast<uint32_t>(old >> 32);
+        w.t0 = static_cast<uint32_t>(old & 0xFFFFFFFFull);
     }
     __syncthreads();
     // E
@@ -199,50 +223,43 @@ __global__ void __launch_bounds__(PLAN_THREADS) k_eng_plan(EngPtrs p) {
     // F
     for (uint32_t idx = tid; idx < NI; idx += PLAN_THREADS) {
         const uint32_t s = idx / static_cast<uint32_t>(RUN_MAX_PEND);
-        const int j = static_cast<int>(idx % static_cast<uint32_t>(RUN_MAX_PEND));
+        const uint32_t j = idx % static_cast<uint32_t>(RUN_MAX_PEND);
         const EngPlanScratch& sc = p.scratch[s];
-        if (!sc.planned) continue;
-        const RunState& o = p.states[s];
-        if (j >= o.n_pend) continue;
+        if (!sc.planned || j >= sc.n_works) continue;
+        const EngWorkPlan w = sc.w[j];
         const EngMeta& m = p.meta[s];
-        const int l = o.pend[j].level, e = o.pend[j].est;
-        const uint64_t n = o.pend[j].n;
-        const EngLevelInfo in = p.info[(s * LV + l) * 3u + e];
-        const uint32_t c = in.cls;
-        const uint64_t begin = o.sums[l][e].n;
-        const WorkSplit sp = sc.sp[j];
-        const uint32_t gw = H.class_work_off[c] + sc.iw[j];
-        const uint32_t t0 = sc.t0[j];
+        const uint32_t c = w.cls;
+        const uint32_t gw = H.class_work_off[c] + w.iw;
         WorkDev W;
-        W.lvl = (s * LV + static_cast<uint32_t>(l)) * 3u + static_cast<uint32_t>(e);
-        W.c2 = stream_c2(l, e);
+        W.lvl = (s * LV + static_cast<uint32_t>(w.level)) * 3u + static_cast<uint32_t>(w.est);
+        W.c2 = stream_c2(w.level, w.est);
         W.c3 = m.c3;
         W.k0 = m.k0;
         W.k1 = m.k1;
         W.pad0 = 0;
-        W.path_begin = begin;
-        W.path_end = begin + n;
+        W.path_begin = w.begin;
+        W.path_end = w.begin + w.n;
         W.debug = 0;
         W.zbuf = 0;
         W.jbuf = 0;
         p.works[gw] = W;
         WorkTilesDev wt;
-        wt.g0 = sp.g0;
-        wt.g1 = sp.g1;
-        wt.per = sp.per;
+        wt.g0 = w.sp.g0;
+        wt.g1 = w.sp.g1;
+        wt.per = w.sp.per;
         wt.work = gw;
-        wt.tile_end = t0 + static_cast<uint32_t>(sp.nt);
-        wt.slot_begin = H.class_slot_off[c] + t0;
+        wt.tile_end = w.t0 + static_cast<uint32_t>(w.sp.nt);
+        wt.slot_begin = H.class_slot_off[c] + w.t0;
         wt.pad = 0;
         p.wtiles[gw] = wt;
         EngReduce rd;
         rd.slot_begin = wt.slot_begin;
-        rd.slot_end = wt.slot_begin + static_cast<uint32_t>(sp.nt);
-        rd.kind = in.kind;
+        rd.slot_end = wt.slot_begin + static_cast<uint32_t>(w.sp.nt);
+        rd.kind = w.kind;
         rd.run = s;
-        rd.level = l;
-        rd.est = e;
-        rd.n = n;
+        rd.level = w.level;
+        rd.est = w.est;
+        rd.n = w.n;
         p.red[gw] = rd;
     }
     __syncthreads();
