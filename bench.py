@@ -109,8 +109,9 @@ def make_items(M, prob, prec_a, prec_c, Na, Nc, offset):
 KERNEL_SOURCES = ("paper_2502_07123_amd/csrc/kernels.hip", "paper_2502_07123_amd/csrc/kernels.hpp",
                   "paper_2502_07123_amd/csrc/common.hpp", "paper_2502_07123_amd/csrc/device/paths.hpp",
                   "paper_2502_07123_amd/csrc/device/philox.hpp", "paper_2502_07123_amd/csrc/device/norminv.hpp",
-                  "paper_2502_07123_amd/csrc/device/fixed.hpp")
+                  "paper_2502_07123_amd/csrc/device/fixed.hpp", "paper_2502_07123_amd/csrc/device/reduce.hpp")
 TRAFFIC_RECORD = "profiles/k_paths_approx_milstein_euro_L0_8_hbm_traffic.md"
+SQ_RECORD = "profiles/k_paths_nested_milstein_euro_L0_8_sq_counters.md"
 
 
 def kernel_source_hash():
@@ -122,20 +123,36 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def _record(path, tag, kernel):
+    """The JSON record after `tag` in a committed profile summary, if it is for
+    `kernel` and the kernel sources have not changed since it was taken."""
+    path = os.path.join(ROOT, path)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith(tag):
+            rec = json.loads(line[len(tag):])
+            if rec.get("source_sha256") != kernel_source_hash() or rec.get("kernel") != kernel:
+                return None
+            return rec
+    return None
+
+
+def recorded_sq(kernel):
+    """VALU busy and issue-cost utilisation of `kernel` from the committed SQ counter
+    pass (definitions in that summary), or None once the kernel sources changed."""
+    rec = _record(SQ_RECORD, "sq_record: ", kernel)
+    return None if rec is None else {"valu_busy": rec["valu_busy"], "issue_cost_util": rec["issue_cost_util"]}
+
+
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (scaled by the copy-probe factors recorded there), or None
     when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_RECORD)
-    if not os.path.exists(path):
+    rec = _record(TRAFFIC_RECORD, "traffic_record: ", kernel)
+    if rec is None:
         return None
-    for line in open(path):
-        if line.startswith("traffic_record: "):
-            rec = json.loads(line[len("traffic_record: "):])
-            if rec.get("source_sha256") != kernel_source_hash() or rec.get("kernel") != kernel:
-                return None
-            return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
-    return None
+    return rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"]
 
 
 def combine_np(S, scale):
@@ -349,11 +366,15 @@ def main():
     # the kernel's time per step (its launches of one step together cover the mix)
     avg_s = dom["ms"] / args.steps * 1e-3
     achieved = ops / avg_s
+    kname = (f"k_paths<{dom['estimator']}, {dom['arith']}, {'true' if dom['scheme'] else 'false'}, "
+             f"{dom['payoffs']}, {'true' if dom['track'] else 'false'}, {dom['fields']}>")
+    sq = recorded_sq(kname)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak_valu() / 1e12,
                 "unit": "Tlane-op/s", "frac": achieved / peak_valu(),
-                "traffic": recorded_traffic(f"k_paths<{dom['estimator']}, {dom['arith']}, "
-                                            f"{'true' if dom['scheme'] else 'false'}, {dom['payoffs']}, "
-                                            f"{'true' if dom['track'] else 'false'}, {dom['fields']}>"),
+                "traffic": recorded_traffic(kname),
+                # from the committed SQ pass of the same kernel (null once its sources change)
+                "valu_busy": None if sq is None else sq["valu_busy"],
+                "issue_cost_util": None if sq is None else sq["issue_cost_util"],
                 "kernel": {"estimator": dom["estimator"], "fields": dom["fields"],
                            "launches_per_step": dom["launches"] / args.steps,
                            "avg_launch_ms": dom["ms"] / dom["launches"],
