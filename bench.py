@@ -740,7 +740,7 @@ def batch(M, ctx, costs, eps_list, n_opt=256, drivers=("engine",)):
                             "rms_err_over_eps": float(np.sqrt(np.mean(np.square(errs)))),
                             "first_call_seconds": first[mode]})
                 print(json.dumps({"batch": out[-1]}), file=sys.stderr, flush=True)
-    ctx.set_driver(True)
+    ctx.set_driver("auto")
     return out
 
 
@@ -834,7 +834,7 @@ def main_workloads(args):
     if args.serving:
         line["serving"] = serving(M, ctx, costs, [float(x) for x in args.serve_rates.split(",")],
                                   args.serve_seconds, drivers=tuple(args.drivers.split(",")))
-        ctx.set_driver(True)
+        ctx.set_driver("auto")
     if args.per_level:
         line["per_level_path_steps_per_s"] = per_level(M, ctx)
     if args.fixed_sweep:

@@ -386,19 +386,25 @@ typedef struct mlmc_result {
     mlmc_level_stats level[MLMC_MAX_LEVELS];
 } mlmc_result;
 
-/* Who drives the estimates' sweeps.  1 (the default): the device sweep engine --
+/* Who drives the estimates' sweeps.  MLMC_DRIVER_ENGINE: the device sweep engine --
  * each option's run state (level sums, sample counts = the next path index of each
  * uniform stream, the driver's decisions) stays in device memory; one sweep of all
  * options is one replay of a HIP graph that computes every run's next samples
  * (pilot, per-level estimator, optimal allocation, bias test) on the device, plans
  * their tiles, runs the path kernels and adds each work's fixed-order sums into its
  * run; the host only replays it, prepares the levels a run reaches and collects
- * finished runs.  0: the host computes each sweep's works from downloaded sums and
- * launches them (a launch sequence per sweep).  Both give the same results bit for
+ * finished runs.  MLMC_DRIVER_HOST: the host computes each sweep's works from
+ * downloaded sums and launches them (a launch sequence per sweep, with only the
+ * kernel classes that have work).  MLMC_DRIVER_AUTO (the default): the engine for
+ * mlmc_estimate_batch calls of at least MLMC_ENGINE_MIN_RUNS options, the host
+ * otherwise and for the server (the engine's sweep has a fixed cost of a few hundred
+ * microseconds that few runs do not amortise).  All give the same results bit for
  * bit (same decisions on the same sums, same tiles, same reductions).  A workspace
  * too small for the engine's arrays falls back to host-driven sweeps.  Errors:
  * MLMC_E_INVALID, MLMC_E_BUSY (a server is running). */
-mlmc_status mlmc_set_driver(mlmc_context* ctx, int32_t engine);
+enum { MLMC_DRIVER_HOST = 0, MLMC_DRIVER_ENGINE = 1, MLMC_DRIVER_AUTO = 2 };
+#define MLMC_ENGINE_MIN_RUNS 64
+mlmc_status mlmc_set_driver(mlmc_context* ctx, int32_t driver);
 
 /* One option, one payoff (single bit of payoff_mask).  Errors as
  * mlmc_level_sums plus MLMC_E_INVALID for the run config. */

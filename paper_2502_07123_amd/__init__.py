@@ -124,8 +124,10 @@ class Context:
         return t.as_dict()
 
     def set_driver(self, engine=True):
-        """Estimates' sweeps on the device sweep engine (True) or planned on the host."""
-        check(lib().mlmc_set_driver(self.h, 1 if engine else 0), self.h)
+        """Estimates' sweeps on the device sweep engine (True), planned on the host
+        (False), or "auto" (the default: the engine for batches of at least
+        MLMC_ENGINE_MIN_RUNS options)."""
+        check(lib().mlmc_set_driver(self.h, 2 if engine == "auto" else (1 if engine else 0)), self.h)
 
     def set_timing(self, on=True):
         check(lib().mlmc_set_timing(self.h, 1 if on else 0), self.h)

@@ -849,7 +849,7 @@ mlmc_status estimate_batch(mlmc_context* ctx, uint32_t n, const mlmc_problem* pr
     }
     if (ctx->ws_held) return fail(ctx, MLMC_E_BUSY, "a running server's sweep engine holds the workspace");
     mlmc_status s = MLMC_E_NOMEM;
-    if (ctx->driver == 1) {
+    if (ctx->driver == MLMC_DRIVER_ENGINE || (ctx->driver == MLMC_DRIVER_AUTO && n >= MLMC_ENGINE_MIN_RUNS)) {
         // the device sweep engine owns the workspace while it runs
         std::lock_guard<std::mutex> lock(ctx->dev_mtx);
         s = drain_flights(ctx);
@@ -1173,12 +1173,13 @@ mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* 
     return mlmc_get_tuning(ctx, out);
 }
 
-mlmc_status mlmc_set_driver(mlmc_context* ctx, int32_t engine) {
+mlmc_status mlmc_set_driver(mlmc_context* ctx, int32_t driver) {
     if (!ctx) return MLMC_E_INVALID;
-    if (engine != 0 && engine != 1) return fail(ctx, MLMC_E_INVALID, "driver must be 0 (host) or 1 (device engine)");
+    if (driver != MLMC_DRIVER_HOST && driver != MLMC_DRIVER_ENGINE && driver != MLMC_DRIVER_AUTO)
+        return fail(ctx, MLMC_E_INVALID, "driver must be 0 (host), 1 (device engine) or 2 (auto)");
     if (ctx->server) return fail(ctx, MLMC_E_BUSY, "a server is running");
     std::lock_guard<std::mutex> lock(ctx->dev_mtx);
-    ctx->driver = engine;
+    ctx->driver = driver;
     return MLMC_OK;
 }
 

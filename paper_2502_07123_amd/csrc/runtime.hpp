@@ -122,7 +122,7 @@ struct mlmc_context {
     // device sweep engines of recent batches of estimates (kept for their graphs;
     // each lays its arrays over the workspace while it runs)
     std::vector<std::unique_ptr<mlmc::Engine>> engines;
-    int driver = 1;                 // estimates: 1 device sweep engine, 0 host-driven sweeps
+    int driver = MLMC_DRIVER_AUTO;  // who drives estimates' sweeps (mlmc_set_driver)
     bool ws_held = false;           // a server's sweep engine holds the workspace
     uint64_t tune_key() const;      // the launch geometry, as one number
     // per-context cache of prepared levels (key: problem, level, precision, estimator)

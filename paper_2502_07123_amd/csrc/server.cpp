@@ -110,7 +110,9 @@ mlmc_status Server::land(bool& progressed) {
             auto it = std::find_if(ctx->flights.begin(), ctx->flights.end(),
                                    [&](const Flight& f) { return f.ticket == sf.ticket; });
             if (it != ctx->flights.end()) {
+                // both streams' parts must be complete: landing waits on each
                 if (hipEventQuery(it->done) == hipErrorNotReady) return MLMC_OK;
+                if (it->done_aux && hipEventQuery(it->done_aux) == hipErrorNotReady) return MLMC_OK;
                 for (;;) {                        // land everything up to and including it
                     const uint64_t t = ctx->flights.front().ticket;
                     drain_oldest(ctx);
@@ -570,7 +572,7 @@ mlmc_status mlmc_server_start(mlmc_context* ctx, const mlmc_server_config* cfg) 
     srv->ctx = ctx;
     srv->cfg = *cfg;
     bool engine = false;
-    if (ctx->driver == 1) {
+    if (ctx->driver == MLMC_DRIVER_ENGINE) {
         const mlmc_status s = srv->engine_start();
         if (s == MLMC_OK) engine = true;
         else if (s != MLMC_E_NOMEM) return s;

@@ -186,15 +186,17 @@ def _mix():
     return out
 
 
+@pytest.mark.parametrize("drv", ["engine", "host"])
 @pytest.mark.parametrize("max_active,ws", [(1, 512 << 20), (64, 512 << 20), (4, 1 << 20)],
                          ids=["1-slot", "64-slots", "4-slots-1MiB"])
-def test_server_results_equal_each_alone(ctx, max_active, ws):
+def test_server_results_equal_each_alone(ctx, max_active, ws, drv):
     """Requests submitted in two waves (the second while the first run) with mixed
     eps and estimators: each result equals mlmc_estimate of the same request alone,
     also with one slot and with a 1 MiB workspace (plans of several launch
-    sequences)."""
+    sequences), with the runs in device engine slots or planned on the host."""
     import time
     c = ctx if ws == (512 << 20) else M.Context(0, workspace_bytes=ws)
+    c.set_driver(drv == "engine")
     try:
         cfg, _, _ = _configs(True, "milstein", "fp32", eps=0.003)
         reqs = _mix()
@@ -220,6 +222,7 @@ def test_server_results_equal_each_alone(ctx, max_active, ws):
             for k in ("estimate", "variance", "L", "levels", "path_steps"):
                 assert got[t][k] == a[k], k
     finally:
+        c.set_driver("auto")
         if c is not ctx:
             c.close()
 

@@ -104,6 +104,7 @@ def test_engine_small_workspace_falls_back():
     cfg = _cfg(True, eps=0.004)
     prob = M.make_problem("milstein", ("euro",), **EURO)
     with M.Context(0, workspace_bytes=1 << 20) as small, M.Context(0, workspace_bytes=256 << 20) as big:
+        small.set_driver(True)
         a = small.estimate_batch(_options(40), cfg, SEED)
         big.set_driver(False)
         b = big.estimate_batch(_options(40), cfg, SEED)
@@ -129,3 +130,21 @@ def test_engine_reused_after_another_engine(ctx):
         again = ctx.estimate(prob, nested, SEED, option=3)
         _same(ref, first, arith)
         _same(ref, again, arith + " after another engine")
+
+
+def test_auto_driver_equals_both():
+    """The default driver (the engine for batches of at least MLMC_ENGINE_MIN_RUNS
+    options, host-planned sweeps below) gives the results of either driver."""
+    cfg = _cfg(True, eps=0.004, L_max=10, packed=True)
+    with M.Context(0, workspace_bytes=256 << 20) as c:
+        for n in (8, 70):
+            probs = _options(n, seed=11)
+            auto = c.estimate_batch(probs, cfg, SEED)
+            c.set_driver(False)
+            host = c.estimate_batch(probs, cfg, SEED)
+            c.set_driver(True)
+            eng = c.estimate_batch(probs, cfg, SEED)
+            c.set_driver("auto")
+            for i in range(n):
+                _same(auto[i], host[i], f"{n} options, option {i} host")
+                _same(auto[i], eng[i], f"{n} options, option {i} engine")
