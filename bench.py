@@ -256,6 +256,9 @@ def main():
                     help="launch geometry as JSON (fields of mlmc_tuning) in place of the tuner")
     ap.add_argument("--per-level", action="store_true",
                     help="instead: path-steps/s per level for each kernel class")
+    ap.add_argument("--configs", action="store_true",
+                    help="instead: the plain FP64 Euler workload (levels 0..4, 1e5 paths per level) and "
+                         "time to eps at fixed L with table sizes q = 4, 6, 8")
     ap.add_argument("--fixed-sweep", action="store_true",
                     help="instead: the fixed-point workload (Euler, 1e6 paths per level, levels 0..10, "
                          "European + Asian + barrier on the same paths)")
@@ -267,7 +270,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.batch or args.serving or args.per_level or args.fixed_sweep:
+    if args.batch or args.serving or args.per_level or args.fixed_sweep or args.configs:
         return main_workloads(args)
     pool, P = (None, 1) if args.no_cpu else oracle_pool()
     import numpy as np
@@ -818,6 +821,74 @@ def fixed_sweep(M, ctx, n_paths=1_000_000, reps=3):
     return out
 
 
+def plain_fp64_levels(M, ctx, n_paths=100_000, levels=5, reps=5):
+    """Plain MLMC of the European call, Euler, FP64 with the exact FP64 inverse normal
+    on Philox uniforms (seed 1234), levels 0..4, 1e5 paths per level: the per-level
+    sums of P_f - P_c (normalised) and the time of one launch sequence of the five
+    works (HIP-event kernel time and wall time, median of reps)."""
+    import numpy as np
+    import torch
+    prob = M.make_problem("euler", ("euro",), **GBM)
+    prec = M.make_precision("fp64", Q)
+    items = [(prob, l, n_paths, 0, prec, M.EST_PLAIN, SEED, 0) for l in range(levels)]
+    ctx.level_sums_batch(items)                                   # warm
+    walls, kms = [], []
+    for r in range(reps):
+        ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.level_sums_batch(items)
+        walls.append(time.perf_counter() - t0)
+        kms.append(sum(x["ms"] for x in ctx.kernel_stats()))
+        ctx.set_timing(False)
+    steps = sum(n_paths << l for l in range(levels))
+    lv = [{"level": l, "n": res[l]["euro"]["n"], "sum_dP": res[l]["euro"]["sum1"],
+           "sum_dP2": res[l]["euro"]["sum2"]} for l in range(levels)]
+    scale = math.exp(-GBM["r"] * GBM["T"]) * GBM["S0"]
+    est = scale * sum(x["sum_dP"] / x["n"] for x in lv)
+    out = {"workload": "plain MLMC, European call, Euler, FP64 exact normals, levels 0..4, 1e5 paths/level",
+           "levels": lv, "estimate": est, "closed_form": closed_form(dict(GBM, kind="euro")),
+           "wall_ms": float(np.median(walls)) * 1e3, "kernel_ms": float(np.median(kms)),
+           "path_steps": steps, "path_steps_per_s_wall": steps / float(np.median(walls))}
+    print(json.dumps({"plain_fp64_levels": out}), file=sys.stderr, flush=True)
+    return out
+
+
+def tte_table_sizes(M, ctx, costs, qs=(4, 6, 8)):
+    """Time to RMSE eps = 1e-3 (price units) at fixed L = 8, theta = 1 (the default
+    bench's time-to-eps setting), nested with a q-bit table (packed FP32 indices) vs
+    plain FP32, over TTE_SEEDS seeds; RMSE about the level-8 reference."""
+    import numpy as np
+    c_p, c_a, c_c = costs
+    prob = M.make_problem("milstein", ("euro",), **GBM)
+    scale = math.exp(-GBM["r"] * GBM["T"]) * GBM["S0"]
+    ref, ref_se = level_reference(M, ctx, prob, scale)
+    out = {"reference_level_L": ref, "reference_se": ref_se, "seeds": TTE_SEEDS}
+    modes = [(f"nested_q{q}", True, q) for q in qs] + [("plain_fp32", False, 8)]
+    for name, nested, q in modes:
+        prec = M.make_precision("fp32", q, packed=True)
+        # the approximate estimator's cost per path-step at this q (the packed fields change it)
+        ca = calibrate(M, ctx, prob, prec, M.make_precision("fp32", q))[0] if nested else c_a
+        cfg = M.make_run_config(EPS, nested=nested, eps_units="absolute", n_pilot=TTE_PILOT, theta=1.0,
+                                L_min=8, L_max=8, costs=(c_p, ca, c_c), plain_arith="fp32", prec=prec)
+        ctx.estimate(prob, cfg, SEED + 1)
+        ts, ests = [], []
+        for rep in range(TTE_SEEDS):
+            t0 = time.perf_counter()
+            r = ctx.estimate(prob, cfg, SEED + 2 + rep)
+            ts.append(time.perf_counter() - t0)
+            ests.append(r["estimate"])
+        e = np.asarray(ests)
+        rmse = float(np.sqrt(np.mean((e - ref) ** 2)))
+        ci = [rmse * math.sqrt(TTE_SEEDS / CHI2_HI), rmse * math.sqrt(TTE_SEEDS / CHI2_LO)]
+        out[name] = {"q": q, "seconds": float(np.median(ts)), "rmse": rmse, "rmse_ci95": ci,
+                     "rmse_within_eps": ci[0] <= EPS, "cost_approx_ns": ca}
+        print(json.dumps({"tte_q": {name: out[name]}}), file=sys.stderr, flush=True)
+    for q in qs:
+        out[f"nested_q{q}"]["speedup_vs_plain_fp32"] = out["plain_fp32"]["seconds"] / out[f"nested_q{q}"]["seconds"]
+    return out
+
+
 def main_workloads(args):
     """--batch / --serving: one JSON line with the batched and/or served workloads."""
     import torch
@@ -839,6 +910,9 @@ def main_workloads(args):
         line["per_level_path_steps_per_s"] = per_level(M, ctx)
     if args.fixed_sweep:
         line["fixed_sweep"] = fixed_sweep(M, ctx)
+    if args.configs:
+        line["plain_fp64_levels"] = plain_fp64_levels(M, ctx)
+        line["tte_table_sizes"] = tte_table_sizes(M, ctx, (c_p, c_a, c_c))
     torch.cuda.synchronize()
     print(json.dumps(line))
     ctx.close()
