@@ -854,6 +854,39 @@ def plain_fp64_levels(M, ctx, n_paths=100_000, levels=5, reps=5):
     return out
 
 
+def tte_methods(M, ctx, costs, q=8):
+    """Section 3's approximate normals compared on the GPU: Methods 1 (interval
+    means), 2 (sum of two small-table variables, coupled through the permutation)
+    and 3 (dyadic piecewise linear), each expanded to the 2^q-entry table the kernels
+    read (so a path-step costs the same); what differs is the correction variance
+    V^D.  Time to RMSE eps at fixed L = 8 (as tte_table_sizes), and V^D per level
+    from the runs' level sums."""
+    import numpy as np
+    c_p, c_a, c_c = costs
+    prob = M.make_problem("milstein", ("euro",), **GBM)
+    scale = math.exp(-GBM["r"] * GBM["T"]) * GBM["S0"]
+    ref, ref_se = level_reference(M, ctx, prob, scale)
+    out = {"q": q, "reference_level_L": ref, "seeds": TTE_SEEDS}
+    for method in (1, 2, 3):
+        prec = M.make_precision("fp32", q, packed=True, method=method)
+        cfg = M.make_run_config(EPS, nested=True, eps_units="absolute", n_pilot=TTE_PILOT, theta=1.0,
+                                L_min=8, L_max=8, costs=(c_p, c_a, c_c), plain_arith="fp32", prec=prec)
+        ctx.estimate(prob, cfg, SEED + 1)
+        ts, ests, vd = [], [], []
+        for rep in range(TTE_SEEDS):
+            t0 = time.perf_counter()
+            r = ctx.estimate(prob, cfg, SEED + 2 + rep)
+            ts.append(time.perf_counter() - t0)
+            ests.append(r["estimate"])
+            vd.append([lv["var"][M.EST_CORR] for lv in r["levels"][:9]])
+        e = np.asarray(ests)
+        rmse = float(np.sqrt(np.mean((e - ref) ** 2)))
+        out[f"method{method}"] = {"seconds": float(np.median(ts)), "rmse": rmse,
+                                  "V_corr_per_level": [float(x) for x in np.median(np.asarray(vd), axis=0)]}
+        print(json.dumps({"tte_method": {method: out[f"method{method}"]}}), file=sys.stderr, flush=True)
+    return out
+
+
 def tte_table_sizes(M, ctx, costs, qs=(4, 6, 8)):
     """Time to RMSE eps = 1e-3 (price units) at fixed L = 8, theta = 1 (the default
     bench's time-to-eps setting), nested with a q-bit table (packed FP32 indices) vs
@@ -913,6 +946,7 @@ def main_workloads(args):
     if args.configs:
         line["plain_fp64_levels"] = plain_fp64_levels(M, ctx)
         line["tte_table_sizes"] = tte_table_sizes(M, ctx, (c_p, c_a, c_c))
+        line["tte_methods"] = tte_methods(M, ctx, (c_p, c_a, c_c))
     torch.cuda.synchronize()
     print(json.dumps(line))
     ctx.close()
