@@ -86,9 +86,19 @@ __host__ __device__ __forceinline__ double ninv64_central(const NinvArg<double>&
 __host__ __device__ __forceinline__ double ninv64_tail(const NinvArg<double>& a) {
     using namespace ninv64;
     const double t = sqrt(a.w) - T_MID;
-    double p = NINV64_PT[DEG_T];
+#if defined(__HIP_DEVICE_COMPILE__)
+    // The tail runs for about 1e-3 of the inputs: its coefficients are loaded where it
+    // runs (the empty asm hides the table's address, so the loads are not hoisted out
+    // of the callers' loops), which leaves the loops' scalar registers to the central
+    // polynomial instead of spilling them into vector-register lanes.
+    const double* pt = g_ninv64_pt;
+    asm volatile("" : "+s"(pt));
+#else
+    const double* pt = NINV64_PT;
+#endif
+    double p = pt[DEG_T];
 #pragma unroll
-    for (int k = DEG_T - 1; k >= 0; --k) p = fma(p, t, NINV64_PT[k]);
+    for (int k = DEG_T - 1; k >= 0; --k) p = fma(p, t, pt[k]);
     return copysign(p, a.y);
 }
 

@@ -112,7 +112,7 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ co
 // per level in LDS (ya_sample) after the step table.  Same per-path operations,
 // tiles and block reduction as k_paths, so the sums are the same bit for bit.
 template <int EST, int ARITH, bool MIL, int NP, bool TRACK, bool X32>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_exact0(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ counts,
          const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
          const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
