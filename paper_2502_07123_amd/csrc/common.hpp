@@ -164,6 +164,21 @@ struct SlotDev {
     uint64_t n, sat, nonfinite, pad;
 };
 
+// A tile's partial sums: the counts, then each payoff's sums together, on 128-byte
+// boundaries, so that a one-payoff tile's partial is one 128-byte line (written by
+// the path kernel, read by the reduction).
+struct PaySums {
+    double s1, s2, e1, e2;
+    uint64_t i2lo, i2hi;
+    int64_t i1;
+    uint64_t pad;
+};
+struct alignas(128) TileSlot {
+    uint64_t n, sat, nonfinite, pad;
+    PaySums p[NPAY];
+};
+static_assert(sizeof(TileSlot) == 384, "tile slot: three 128-byte lines");
+
 struct ReduceDev {
     uint32_t slot_begin, slot_end;   // this work item's tile slots
     uint32_t kind;                   // sums present: 1 correction, 2 integer, 4 all payoffs

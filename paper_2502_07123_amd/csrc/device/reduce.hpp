@@ -44,15 +44,11 @@ struct RedLds {
     uint64_t c[MAX_WAVES][3];
 };
 
-// Block sum of the per-thread accumulators (butterfly in each wave, then the waves
-// in index order) written by thread 0 to *out; the counts come as 64-bit values.
-// FULL: the whole SlotDev (zeros in the fields the variant does not fill: a work's
-// result); else only the fields the reduction reads (a tile's partial sums).
-template <int NP, bool CORR, bool INTS, bool FULL>
-__device__ __forceinline__ void block_store_counts(Acc<NP>& a, uint64_t cn, uint64_t csat, uint64_t cnf,
-                                                   SlotDev* out, RedLds& r) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = (blockDim.x + 63) >> 6;
+// Wave sums (butterfly) of one wave's accumulators; lane 0 writes them, with the
+// counts as 64-bit values, to row `row` of r.
+template <int NP, bool CORR, bool INTS>
+__device__ __forceinline__ void wave_to_lds(Acc<NP>& a, uint64_t cn, uint64_t csat, uint64_t cnf, RedLds& r,
+                                            uint32_t row) {
     double d[4 * NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -68,73 +64,77 @@ __device__ __forceinline__ void block_store_counts(Acc<NP>& a, uint64_t cn, uint
     const int64_t n = wave_sum(static_cast<int64_t>(cn));
     const int64_t sat = wave_sum(static_cast<int64_t>(csat));
     const int64_t nf = wave_sum(static_cast<int64_t>(cnf));
-    __syncthreads();                           // previous tile's readers are done
-    if (lane == 0) {
+    if ((threadIdx.x & 63u) == 0) {
 #pragma unroll
-        for (int i = 0; i < 4 * NP; ++i) r.d[wave][i] = d[i];
+        for (int i = 0; i < 4 * NP; ++i) r.d[row][i] = d[i];
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            r.i1[wave][p] = INTS ? a.i1[p] : 0;
-            r.lo[wave][p] = INTS ? a.i2lo[p] : 0;
-            r.hi[wave][p] = INTS ? a.i2hi[p] : 0;
+            r.i1[row][p] = INTS ? a.i1[p] : 0;
+            r.lo[row][p] = INTS ? a.i2lo[p] : 0;
+            r.hi[row][p] = INTS ? a.i2hi[p] : 0;
         }
-        r.c[wave][0] = n;
-        r.c[wave][1] = sat;
-        r.c[wave][2] = nf;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        SlotDev s;
-        for (int p = 0; p < NPAY; ++p) {
-            s.s1[p] = s.s2[p] = s.e1[p] = s.e2[p] = 0.0;
-            s.i1[p] = 0;
-            s.i2lo[p] = s.i2hi[p] = 0;
-        }
-        s.n = s.sat = s.nonfinite = s.pad = 0;
-        for (int w = 0; w < nw; ++w) {
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                s.s1[p] += r.d[w][p];
-                s.s2[p] += r.d[w][NP + p];
-                s.e1[p] += r.d[w][2 * NP + p];
-                s.e2[p] += r.d[w][3 * NP + p];
-                s.i1[p] += r.i1[w][p];
-                const uint64_t nlo = s.i2lo[p] + r.lo[w][p];
-                s.i2hi[p] += r.hi[w][p] + (nlo < s.i2lo[p] ? 1u : 0u);
-                s.i2lo[p] = nlo;
-            }
-            s.n += r.c[w][0];
-            s.sat += r.c[w][1];
-            s.nonfinite += r.c[w][2];
-        }
-        if (FULL) {
-            *out = s;
-        } else {
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                out->s1[p] = s.s1[p];
-                out->s2[p] = s.s2[p];
-                if (CORR) {
-                    out->e1[p] = s.e1[p];
-                    out->e2[p] = s.e2[p];
-                }
-                if (INTS) {
-                    out->i1[p] = s.i1[p];
-                    out->i2lo[p] = s.i2lo[p];
-                    out->i2hi[p] = s.i2hi[p];
-                }
-            }
-            out->n = s.n;
-            out->sat = s.sat;
-            out->nonfinite = s.nonfinite;
-        }
+        r.c[row][0] = n;
+        r.c[row][1] = sat;
+        r.c[row][2] = nf;
     }
 }
 
-// a tile's partial sums
+// Rows 0 .. nrows-1 of r added in index order (from zero) into s (all payoffs'
+// fields; zero where the variant has none).
+__device__ __forceinline__ void rows_total(const RedLds& r, uint32_t nrows, int np, SlotDev& s) {
+    for (int p = 0; p < NPAY; ++p) {
+        s.s1[p] = s.s2[p] = s.e1[p] = s.e2[p] = 0.0;
+        s.i1[p] = 0;
+        s.i2lo[p] = s.i2hi[p] = 0;
+    }
+    s.n = s.sat = s.nonfinite = s.pad = 0;
+    for (uint32_t w = 0; w < nrows; ++w) {
+        for (int p = 0; p < np; ++p) {
+            s.s1[p] += r.d[w][p];
+            s.s2[p] += r.d[w][np + p];
+            s.e1[p] += r.d[w][2 * np + p];
+            s.e2[p] += r.d[w][3 * np + p];
+            s.i1[p] += r.i1[w][p];
+            const uint64_t nlo = s.i2lo[p] + r.lo[w][p];
+            s.i2hi[p] += r.hi[w][p] + (nlo < s.i2lo[p] ? 1u : 0u);
+            s.i2lo[p] = nlo;
+        }
+        s.n += r.c[w][0];
+        s.sat += r.c[w][1];
+        s.nonfinite += r.c[w][2];
+    }
+}
+
+// A tile's partial sums: the block sum of the per-thread accumulators (butterfly in
+// each wave, then the waves in index order) written by thread 0 to *out (the
+// fields the variant has).
 template <int NP, bool CORR, bool INTS>
-__device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r) {
-    block_store_counts<NP, CORR, INTS, false>(a, a.n, a.sat, a.nonfinite, out, r);
+__device__ __forceinline__ void block_store(Acc<NP>& a, TileSlot* out, RedLds& r) {
+    __syncthreads();                           // previous readers of r are done
+    wave_to_lds<NP, CORR, INTS>(a, a.n, a.sat, a.nonfinite, r, threadIdx.x >> 6);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        SlotDev s;
+        rows_total(r, (blockDim.x + 63) >> 6, NP, s);
+        out->n = s.n;
+        out->sat = s.sat;
+        out->nonfinite = s.nonfinite;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            PaySums& o = out->p[p];
+            o.s1 = s.s1[p];
+            o.s2 = s.s2[p];
+            if (CORR) {
+                o.e1 = s.e1[p];
+                o.e2 = s.e2[p];
+            }
+            if (INTS) {
+                o.i1 = s.i1[p];
+                o.i2lo = s.i2lo[p];
+                o.i2hi = s.i2hi[p];
+            }
+        }
+    }
 }
 
 // Sums of one work item's tile slots in a fixed order that depends only on the
@@ -142,11 +142,13 @@ __device__ __forceinline__ void block_store(Acc<NP>& a, SlotDev* out, RedLds& r)
 // c = w, w + 8, w + 16, ... in order; a butterfly adds each wave's lanes and the
 // waves are added in index order.  Only the payoffs, correction sums and integer
 // sums of the work's kernel variant are added; the rest of the result is zero.
+// A lane reads the counts and each payoff's sums of its slot as whole 16-byte words
+// of one line.
 constexpr int REDUCE_THREADS = 512;
 constexpr int REDUCE_WAVES = REDUCE_THREADS / 64;
 
 template <int NP, bool CORR, bool INTS>
-__device__ __forceinline__ void reduce_work(const SlotDev* __restrict__ sl, uint32_t ns,
+__device__ __forceinline__ void reduce_work(const TileSlot* __restrict__ sl, uint32_t ns,
                                             SlotDev* __restrict__ dst, RedLds& r) {
     Acc<NP> a;
     acc_zero(a);
@@ -154,27 +156,38 @@ __device__ __forceinline__ void reduce_work(const SlotDev* __restrict__ sl, uint
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
 #pragma unroll 4
     for (uint32_t i = wave * 64u + lane; i < ns; i += REDUCE_THREADS) {
-        const SlotDev& x = sl[i];
+        const TileSlot& x = sl[i];
+        const ulonglong2 c = *reinterpret_cast<const ulonglong2*>(&x.n);
+        n += c.x;
+        sat += c.y;
+        nf += x.nonfinite;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            a.s1[p] += x.s1[p];
-            a.s2[p] += x.s2[p];
+            const double2 s = *reinterpret_cast<const double2*>(&x.p[p].s1);
+            a.s1[p] += s.x;
+            a.s2[p] += s.y;
             if (CORR) {
-                a.e1[p] += x.e1[p];
-                a.e2[p] += x.e2[p];
+                const double2 e = *reinterpret_cast<const double2*>(&x.p[p].e1);
+                a.e1[p] += e.x;
+                a.e2[p] += e.y;
             }
             if (INTS) {
-                a.i1[p] += x.i1[p];
-                const uint64_t lo = a.i2lo[p] + x.i2lo[p];
-                a.i2hi[p] += x.i2hi[p] + (lo < a.i2lo[p] ? 1u : 0u);
+                a.i1[p] += x.p[p].i1;
+                const ulonglong2 w = *reinterpret_cast<const ulonglong2*>(&x.p[p].i2lo);
+                const uint64_t lo = a.i2lo[p] + w.x;
+                a.i2hi[p] += w.y + (lo < a.i2lo[p] ? 1u : 0u);
                 a.i2lo[p] = lo;
             }
         }
-        n += x.n;
-        sat += x.sat;
-        nf += x.nonfinite;
     }
-    block_store_counts<NP, CORR, INTS, true>(a, n, sat, nf, dst, r);
+    __syncthreads();                           // previous readers of r are done
+    wave_to_lds<NP, CORR, INTS>(a, n, sat, nf, r, wave);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        SlotDev s;
+        rows_total(r, REDUCE_WAVES, NP, s);
+        *dst = s;
+    }
 }
 
 }  // namespace mlmc

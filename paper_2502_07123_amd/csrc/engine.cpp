@@ -197,10 +197,10 @@ mlmc_status Engine::layout() {
     const size_t o_tables = o;
     o = al(o + size_t(C) * LV * 2 * tstride);
     const size_t o_slots = o;
-    if (o_slots + 64 * sizeof(SlotDev) > ctx->ws_bytes)
+    if (o_slots + 64 * sizeof(TileSlot) > ctx->ws_bytes)
         return fail(ctx, MLMC_E_NOMEM, "workspace too small for the sweep engine: need " +
-                                           std::to_string(o_slots + 64 * sizeof(SlotDev)) + " bytes");
-    slot_cap = std::min<uint64_t>((ctx->ws_bytes - o_slots) / sizeof(SlotDev), uint64_t(1) << 22);
+                                           std::to_string(o_slots + 64 * sizeof(TileSlot)) + " bytes");
+    slot_cap = std::min<uint64_t>((ctx->ws_bytes - o_slots) / sizeof(TileSlot), uint64_t(1) << 22);
     uint8_t* b = ctx->ws;
     P.hdr = reinterpret_cast<EngHeader*>(b + o_hdr);
     P.states = reinterpret_cast<RunState*>(b + o_states);
@@ -210,7 +210,7 @@ mlmc_status Engine::layout() {
     P.works = reinterpret_cast<WorkDev*>(b + o_works);
     P.wtiles = reinterpret_cast<WorkTilesDev*>(b + o_wt);
     P.red = reinterpret_cast<EngReduce*>(b + o_red);
-    P.slots = reinterpret_cast<SlotDev*>(b + o_slots);
+    P.slots = reinterpret_cast<TileSlot*>(b + o_slots);
     P.status_out = reinterpret_cast<uint32_t*>(b + o_status);
     base = b + o_base;
     jobs = reinterpret_cast<EngTableJob*>(b + o_jobs);

@@ -105,7 +105,7 @@ struct EngPtrs {
     WorkDev* works;             // [max_works]
     WorkTilesDev* wtiles;       // [max_works], each class's in one run (counts[c][2] on)
     EngReduce* red;             // [max_works]
-    SlotDev* slots;             // [slot_cap]
+    TileSlot* slots;            // [slot_cap]
     uint32_t* status_out;       // [slot] status words for the host, then the error word
 };
 

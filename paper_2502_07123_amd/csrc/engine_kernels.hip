@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(REDUCE_THREADS) k_eng_reduce(EngPtrs p) {
     const uint32_t nw = p.hdr->n_works;
     for (uint32_t w = blockIdx.x; w < nw; w += gridDim.x) {
         const EngReduce rd = p.red[w];
-        const SlotDev* sl = p.slots + rd.slot_begin;
+        const TileSlot* sl = p.slots + rd.slot_begin;
         const uint32_t ns = rd.slot_end - rd.slot_begin;
         switch (rd.kind & 3u) {
             case 1: reduce_work<1, true, false>(sl, ns, &res, red); break;

@@ -34,7 +34,7 @@ template <int EST, int ARITH, bool MIL, int NP, bool TRACK, int F, bool X32>
 __global__ void __attribute__((amdgpu_flat_work_group_size(64, max_threads<EST, ARITH, NP>())))
 k_paths(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ counts,
         const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
-        const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
+        const uint8_t* __restrict__ tables, TileSlot* __restrict__ slots) {
     const uint32_t n_wt = counts[0], n_tiles = counts[1];
     wtiles += counts[2];
     using Body = PathBody<EST, ARITH, MIL, NP, TRACK, F, X32>;
@@ -115,7 +115,7 @@ template <int EST, int ARITH, bool MIL, int NP, bool TRACK, bool X32>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_exact0(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ counts,
          const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
-         const uint8_t* __restrict__ tables, SlotDev* __restrict__ slots) {
+         const uint8_t* __restrict__ tables, TileSlot* __restrict__ slots) {
     const uint32_t n_wt = counts[0], n_tiles = counts[1];
     wtiles += counts[2];
     using Body = PathBody<EST, ARITH, MIL, NP, TRACK, 1, X32>;
@@ -200,10 +200,10 @@ k_normals(const TileDev* __restrict__ tiles, uint32_t n_tiles, const WorkDev* __
 }
 
 __global__ void __launch_bounds__(REDUCE_THREADS)
-k_reduce(const SlotDev* __restrict__ slots, const ReduceDev* __restrict__ rds, SlotDev* __restrict__ results) {
+k_reduce(const TileSlot* __restrict__ slots, const ReduceDev* __restrict__ rds, SlotDev* __restrict__ results) {
     __shared__ RedLds red;
     const ReduceDev rd = rds[blockIdx.x];
-    const SlotDev* sl = slots + rd.slot_begin;
+    const TileSlot* sl = slots + rd.slot_begin;
     const uint32_t ns = rd.slot_end - rd.slot_begin;
     SlotDev* dst = results + rd.work;
     switch (rd.kind) {
@@ -229,7 +229,7 @@ k_upload(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, uint32_t 
 
 // ------------------------------------------------------------------ dispatch
 using PathKernel = void (*)(const WorkTilesDev*, const uint32_t*, const WorkDev*, const LevelDev*,
-                            const uint8_t*, SlotDev*);
+                            const uint8_t*, TileSlot*);
 
 namespace {
 struct InfoOf {
@@ -269,7 +269,7 @@ bool has_level0_kernel(const Variant& v) {
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,
                         hipStream_t st, const WorkTilesDev* wtiles, const uint32_t* counts,
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
-                        SlotDev* slots) {
+                        TileSlot* slots) {
     const PathKernel k = reinterpret_cast<PathKernel>(vi.fn);
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds_bytes, st, wtiles, counts, works, levels,
                        tables, slots);
@@ -295,7 +295,7 @@ hipError_t launch_upload(const void* host_src, void* dst, size_t bytes, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
+hipError_t launch_reduce(uint32_t n, hipStream_t st, const TileSlot* slots, const ReduceDev* rds,
                          SlotDev* results) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce, dim3(n), dim3(REDUCE_THREADS), 0, st, slots, rds, results);

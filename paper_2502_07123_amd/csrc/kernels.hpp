@@ -102,7 +102,7 @@ bool has_level0_kernel(const Variant& v);
 hipError_t launch_paths(const VariantInfo& vi, uint32_t grid, uint32_t block, size_t lds_bytes,
                         hipStream_t st, const WorkTilesDev* wtiles, const uint32_t* counts,
                         const WorkDev* works, const LevelDev* levels, const uint8_t* tables,
-                        SlotDev* slots);
+                        TileSlot* slots);
 
 // Philox blocks per tile of the normals-ahead kernel (one per thread of its 256)
 constexpr uint64_t NORMALS_TILE_BLOCKS = 256;
@@ -118,8 +118,9 @@ constexpr uint32_t UPLOAD_THREADS = 256;
 hipError_t launch_upload(const void* host_src, void* dst, size_t bytes, hipStream_t st);
 
 // results[rds[b].work] = fixed-order sum of that work's tile slots (block b of n
-// takes rds[b])
-hipError_t launch_reduce(uint32_t n, hipStream_t st, const SlotDev* slots, const ReduceDev* rds,
+// takes rds[b]); results may be device memory or coherent pinned host memory (the
+// sums then reach the host with the kernel's completion, without a copy)
+hipError_t launch_reduce(uint32_t n, hipStream_t st, const TileSlot* slots, const ReduceDev* rds,
                          SlotDev* results);
 
 }  // namespace mlmc

@@ -425,9 +425,9 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     }
 
     // 3. layout (offsets from the flight's base):
-    //    [results | levels | works | tables | work tiles | reds | normal tiles | slots | normals]
-    const size_t o_res = 0;
-    const size_t o_lvl = align_up(o_res + works.size() * sizeof(SlotDev), 256);
+    //    [levels | works | tables | work tiles | reds | normal tiles | slots | normals]
+    //    (the results go straight to the pinned staging buffer)
+    const size_t o_lvl = 0;
     const size_t o_work = align_up(o_lvl + levels.size() * sizeof(LevelDev), 256);
     const size_t o_tab = align_up(o_work + wdev.size() * sizeof(WorkDev), 256);
     const size_t o_tile = align_up(o_tab + tables.size(), 256);
@@ -449,7 +449,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     // neither stream waits for the other)
     const size_t o_copy = o_end_plan;
     const size_t o_slot = fork ? align_up(o_copy + (o_end_plan - o_lvl), 256) : o_end_plan;
-    size_t o_zb = align_up(o_slot + size_t(n_slots) * sizeof(SlotDev), 256);
+    size_t o_zb = align_up(o_slot + size_t(n_slots) * sizeof(TileSlot), 256);
     std::vector<size_t> zb_off(works.size(), 0);
     for (size_t i = 0; i < works.size(); ++i) {
         if (zb_f32[i] < 0) continue;
@@ -562,26 +562,23 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
                             reinterpret_cast<const uint32_t*>(dp + o_cnt) + g.cnt,
                             reinterpret_cast<const WorkDev*>(dp + o_work),
                             reinterpret_cast<const LevelDev*>(dp + o_lvl), dp + o_tab,
-                            reinterpret_cast<SlotDev*>(d + o_slot)));
+                            reinterpret_cast<TileSlot*>(d + o_slot)));
         if (ctx->timing) HIPCHK(hipEventRecord(tm.e1, gs));
     }
-    const SlotDev* sl_dev = reinterpret_cast<const SlotDev*>(d + o_slot);
-    SlotDev* res_dev = reinterpret_cast<SlotDev*>(d + o_res);
+    // the reduction writes each work's sums into the pinned staging buffer (coherent
+    // host memory): they are on the host when the kernel completes
+    const TileSlot* sl_dev = reinterpret_cast<const TileSlot*>(d + o_slot);
+    SlotDev* res_host = reinterpret_cast<SlotDev*>(h + f.down_off);
     if (fork) {
-        // each stream reduces and downloads its own works' results (positions
-        // [0, n_red_aux) on the second stream) and records its own completion event
-        const size_t sz = sizeof(SlotDev);
-        HIPCHK(launch_reduce(n_red_aux, sa, sl_dev, reinterpret_cast<const ReduceDev*>(da + o_red), res_dev));
-        HIPCHK(hipMemcpyAsync(h + f.down_off, d + o_res, n_red_aux * sz, hipMemcpyDeviceToHost, sa));
+        // each stream reduces its own works (positions [0, n_red_aux) on the second
+        // stream) and records its own completion event
+        HIPCHK(launch_reduce(n_red_aux, sa, sl_dev, reinterpret_cast<const ReduceDev*>(da + o_red), res_host));
         HIPCHK(hipEventRecord(f.done_aux, sa));
         HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()) - n_red_aux, s, sl_dev,
-                             reinterpret_cast<const ReduceDev*>(d + o_red) + n_red_aux, res_dev));
-        HIPCHK(hipMemcpyAsync(h + f.down_off + n_red_aux * sz, d + o_res + n_red_aux * sz,
-                              down_bytes - n_red_aux * sz, hipMemcpyDeviceToHost, s));
+                             reinterpret_cast<const ReduceDev*>(d + o_red) + n_red_aux, res_host));
     } else {
         HIPCHK(launch_reduce(static_cast<uint32_t>(works.size()), s, sl_dev,
-                             reinterpret_cast<const ReduceDev*>(d + o_red), res_dev));
-        HIPCHK(hipMemcpyAsync(h + f.down_off, d + o_res, down_bytes, hipMemcpyDeviceToHost, s));
+                             reinterpret_cast<const ReduceDev*>(d + o_red), res_host));
     }
     HIPCHK(hipEventRecord(f.done, s));
     return MLMC_OK;

@@ -23,7 +23,7 @@
 namespace mlmc {
 
 // 4 MiB per GPU: the plan (under 48 KiB with the largest table) and up to
-// STATIC_MAX_TILES partial sums of 312 bytes.
+// STATIC_MAX_TILES tile partials of 384 bytes (3 MiB).
 constexpr size_t SCRATCH_BYTES = size_t(4) << 20;
 constexpr uint64_t STATIC_MAX_TILES = 8192;
 static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
@@ -159,7 +159,7 @@ extern "C" mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t 
     const size_t o_cnt = align256(o_red + sizeof(ReduceDev));
     const size_t o_tab = align256(o_cnt + 4 * sizeof(uint32_t));
     const size_t o_slot = align256(o_tab + lp.table.size());
-    const size_t need = o_slot + sp.nt * sizeof(SlotDev);
+    const size_t need = o_slot + sp.nt * sizeof(TileSlot);
     if (sp.nt > STATIC_MAX_TILES || need > SCRATCH_BYTES)
         return static_fail(MLMC_E_NOMEM, "mlmc_level_sums_static: needs " + std::to_string(need) +
                                              " bytes of its " + std::to_string(SCRATCH_BYTES) + "-byte scratch");
@@ -213,9 +213,9 @@ extern "C" mlmc_status mlmc_level_sums_static(const mlmc_problem* prob, int32_t 
     e = launch_paths(vi, grid, block, lds, st, reinterpret_cast<const WorkTilesDev*>(d + o_tile),
                      reinterpret_cast<const uint32_t*>(d + o_cnt), reinterpret_cast<const WorkDev*>(d + o_work),
                      reinterpret_cast<const LevelDev*>(d + o_lvl), d + o_tab,
-                     reinterpret_cast<SlotDev*>(d + o_slot));
+                     reinterpret_cast<TileSlot*>(d + o_slot));
     if (e == hipSuccess)
-        e = launch_reduce(1, st, reinterpret_cast<const SlotDev*>(d + o_slot),
+        e = launch_reduce(1, st, reinterpret_cast<const TileSlot*>(d + o_slot),
                           reinterpret_cast<const ReduceDev*>(d + o_red), reinterpret_cast<SlotDev*>(d + o_res));
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_sums_out, dim3(1), dim3(64), 0, st, reinterpret_cast<const SlotDev*>(d + o_res),
