@@ -131,12 +131,14 @@ __host__ __device__ __forceinline__ T multiplier_lp(T z, T con1, T con2, T con3,
     return s;
 }
 
+// two binary16 values, operated on as packed math on the device (v_pk_*_f16)
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
 #if defined(__HIP_DEVICE_COMPILE__)
 // FP16 on the device: the coarse step's independent operation pairs as packed math,
 // (mul1, zsq) = (con2, zs) * (zs, zs) and (sum1, zm1) = (con1, -c) + (mul1, zsq), each
 // lane rounded as the scalar operation (IEEE, per element), so the result equals
 // multiplier_lp<MIL, _Float16> bit for bit.
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 template <bool MIL>
 __device__ __forceinline__ _Float16 multiplier_h2(_Float16 z, _Float16 con1, _Float16 con2, _Float16 con3,
                                                   _Float16 c) {
@@ -806,6 +808,77 @@ struct PathBody {
             for (int j = 0; j < WPB; ++j) approx_step(L, tab, k[j], (j & 1) != 0, ap, ax);
         }
         finish(L, W, 0, ex, ap, ax, 0u, 0u, acc);
+    }
+
+    // ---- FP16, two paths per lane: a thread's next two whole groups ga < gb above
+    // level 0 (no records, no path functionals) advance together, each operation of
+    // the two paths' chains one packed instruction (v_pk_mul_f16 / v_pk_add_f16,
+    // rounded per element as the scalar operation), and finish in the order ga, gb:
+    // the per-path values and the order of accumulation of run_group_fast on ga, then
+    // on gb.
+    static constexpr bool PAIR = FASTG && HALF && !TRACK;
+
+    __device__ __forceinline__ static void run_group_pair(const LevelDev& L, const WorkDev& W, uint64_t ga,
+                                                          uint64_t gb, const void* tab, Acc<NP>& acc) {
+        if constexpr (PAIR) {
+            // long paths (a group is one path), both in the work's range
+            if (L.level >= WPB_TZ && !W.debug && ga >= W.path_begin && gb < W.path_end) {
+                long_path_pair(L, W, ga, gb, tab, acc);
+                return;
+            }
+        }
+        run_group_fast(L, W, ga, tab, acc);
+        run_group_fast(L, W, gb, tab, acc);
+    }
+
+    __device__ __forceinline__ static void long_path_pair(const LevelDev& L, const WorkDev& W, uint64_t ga,
+                                                          uint64_t gb, const void* tab, Acc<NP>& acc) {
+#pragma clang fp contract(off)
+        const uint32_t nblk = (1u << L.level) / WPB;
+        const LpConst<_Float16> c = lp_const<_Float16>(L);
+        const half2v con1c = {c.con1c, c.con1c}, con2 = {c.con2, c.con2}, con3 = {c.con3, c.con3};
+        const half2v two = {_Float16(2), _Float16(2)};
+        const TabPair<_Float16>* T = static_cast<const TabPair<_Float16>*>(tab);
+        half2v xf = {_Float16(1), _Float16(1)}, xc = xf, zp = {_Float16(0), _Float16(0)};
+        uint64_t ba = ga * nblk, bb = gb * nblk;
+        for (uint32_t ib = 0; ib < nblk; ++ib, ++ba, ++bb) {
+            uint32_t ka[WPB], kb[WPB];
+            block_indices(W, ba, L.q, ka);
+            block_indices(W, bb, L.q, kb);
+#pragma unroll
+            for (int j = 0; j < WPB; ++j) {
+                const TabPair<_Float16> ea = T[ka[j]], eb = T[kb[j]];
+                const half2v z = {ea.z, eb.z}, sk = {ea.s, eb.s};
+                const half2v mul2 = xf * sk;                    // fine: x + x s_k
+                xf = xf + mul2;
+                if ((j & 1) == 0) {
+                    zp = z;
+                } else {                                        // coarse: x + x m(zp + z)
+                    const half2v zs = zp + z;
+                    const half2v mul1 = con2 * zs;
+                    half2v m = con1c + mul1;
+                    if (MIL) {
+                        const half2v zsq = zs * zs;
+                        const half2v zm1 = zsq - two;
+                        const half2v mul3 = con3 * zm1;
+                        m = m + mul3;
+                    }
+                    const half2v mc = xc * m;
+                    xc = xc + mc;
+                }
+            }
+        }
+        FSide<ExactT> ex;
+        XSide ax;
+        FSide<_Float16> a, b;
+        a.init();
+        b.init();
+        a.xf = xf.x;
+        a.xc = xc.x;
+        b.xf = xf.y;
+        b.xc = xc.y;
+        finish(L, W, 0, ex, a, ax, 0u, 0u, acc);
+        finish(L, W, 0, ex, b, ax, 0u, 0u, acc);
     }
 
     // Philox block b of W's stream for the exact-normal loops.  The keys are marked

@@ -92,6 +92,13 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ co
             // normals computed ahead: a group is one path
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)
                 Body::run_path_buffered(L, W, g, s_tab, acc);
+        } else if (Body::PAIR && L.level >= 1 && !W.debug) {
+            // a thread's groups g, g + B, g + 2B, ... two at a time (packed FP16), in
+            // the same order
+            uint64_t g = td.group_begin + threadIdx.x;
+            for (; g + blockDim.x < gend; g += 2u * blockDim.x)
+                Body::run_group_pair(L, W, g, g + blockDim.x, s_tab, acc);
+            if (g < gend) Body::run_group_fast(L, W, g, s_tab, acc);
         } else if ((Body::FASTG || Body::EXG) && L.level >= 1 && !W.debug) {
             // whole groups above level 0: path boundaries by construction
             for (uint64_t g = td.group_begin + threadIdx.x; g < gend; g += blockDim.x)

@@ -107,6 +107,22 @@ def test_level0_exact_loop_equals_debug_run(ctx, est, arith, method, q):
         assert a == b, (est, arith, method, q, pays)
 
 
+@pytest.mark.parametrize("scheme", ["euler", "milstein"])
+@pytest.mark.parametrize("packed", [True, False], ids=["packed", "unpacked"])
+def test_fp16_two_paths_per_lane_equal_debug_run(ctx, scheme, packed):
+    """FP16 approximate paths above level 0 run two per lane (packed binary16
+    arithmetic) without a debug buffer: the same sums as the one-path-per-lane code of
+    a debug run, bit for bit, over odd numbers of groups per thread and ragged path
+    ranges; with path functionals (Asian, barrier) a lane keeps one path."""
+    prec = M.make_precision("fp16", 8, packed)
+    for pays in (("euro",), ("euro", "digital"), PAYS):
+        prob = M.make_problem(scheme, pays, **GBM)
+        for level, n, off in ((2, 70_001, 3), (4, 50_003, 11), (5, 20_011, 0), (8, 3_001, 7)):
+            a = ctx.level_sums(prob, level, n, off, prec, M.EST_APPROX, SEED)
+            b, _ = ctx.level_sums(prob, level, n, off, prec, M.EST_APPROX, SEED, debug=True)
+            assert a == b, (scheme, packed, pays, level)
+
+
 def test_repeatable_and_offset_split(ctx):
     """Bit-identical repeated runs; exact integer sums split over two path ranges add up."""
     prob = M.make_problem("euler", ("euro", "asian"), **GBM)
