@@ -147,6 +147,40 @@ __device__ __forceinline__ void block_store(Acc<NP>& a, TileSlot* out, RedLds& r
 constexpr int REDUCE_THREADS = 512;
 constexpr int REDUCE_WAVES = REDUCE_THREADS / 64;
 
+// The fields of one tile slot that a reduction adds.
+template <int NP, bool CORR, bool INTS>
+struct SlotPart {
+    ulonglong2 c;                  // n, sat
+    uint64_t nf;
+    double2 s[NP], e[NP];          // (s1, s2), (e1, e2)
+    ulonglong2 w[NP];              // (i2lo, i2hi)
+    int64_t i1[NP];
+};
+
+template <int NP, bool CORR, bool INTS>
+__device__ __forceinline__ void load_part(const TileSlot& x, SlotPart<NP, CORR, INTS>& v) {
+    v.c = *reinterpret_cast<const ulonglong2*>(&x.n);
+    v.nf = x.nonfinite;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        v.s[p] = *reinterpret_cast<const double2*>(&x.p[p].s1);
+        if (CORR) v.e[p] = *reinterpret_cast<const double2*>(&x.p[p].e1);
+        if (INTS) {
+            v.w[p] = *reinterpret_cast<const ulonglong2*>(&x.p[p].i2lo);
+            v.i1[p] = x.p[p].i1;
+        }
+    }
+}
+
+// Slots in flight per lane of a reduction: a lane loads its next red_batch slots
+// (those below ns) before adding them in order, so that a work with thousands of
+// tiles is not bound by one load's latency per slot (one-payoff sums: 8 slots;
+// all five payoffs: 1, within the registers).
+template <int NP>
+constexpr uint32_t red_batch() {
+    return NP == 1 ? 8u : 1u;
+}
+
 template <int NP, bool CORR, bool INTS>
 __device__ __forceinline__ void reduce_work(const TileSlot* __restrict__ sl, uint32_t ns,
                                             SlotDev* __restrict__ dst, RedLds& r) {
@@ -154,29 +188,32 @@ __device__ __forceinline__ void reduce_work(const TileSlot* __restrict__ sl, uin
     acc_zero(a);
     uint64_t n = 0, sat = 0, nf = 0;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-#pragma unroll 4
-    for (uint32_t i = wave * 64u + lane; i < ns; i += REDUCE_THREADS) {
-        const TileSlot& x = sl[i];
-        const ulonglong2 c = *reinterpret_cast<const ulonglong2*>(&x.n);
-        n += c.x;
-        sat += c.y;
-        nf += x.nonfinite;
+    constexpr uint32_t RED_BATCH = red_batch<NP>();
+    for (uint32_t i0 = wave * 64u + lane; i0 < ns; i0 += RED_BATCH * REDUCE_THREADS) {
+        SlotPart<NP, CORR, INTS> v[RED_BATCH];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const double2 s = *reinterpret_cast<const double2*>(&x.p[p].s1);
-            a.s1[p] += s.x;
-            a.s2[p] += s.y;
-            if (CORR) {
-                const double2 e = *reinterpret_cast<const double2*>(&x.p[p].e1);
-                a.e1[p] += e.x;
-                a.e2[p] += e.y;
-            }
-            if (INTS) {
-                a.i1[p] += x.p[p].i1;
-                const ulonglong2 w = *reinterpret_cast<const ulonglong2*>(&x.p[p].i2lo);
-                const uint64_t lo = a.i2lo[p] + w.x;
-                a.i2hi[p] += w.y + (lo < a.i2lo[p] ? 1u : 0u);
-                a.i2lo[p] = lo;
+        for (uint32_t b = 0; b < RED_BATCH; ++b)
+            if (i0 + b * REDUCE_THREADS < ns) load_part(sl[i0 + b * REDUCE_THREADS], v[b]);
+#pragma unroll
+        for (uint32_t b = 0; b < RED_BATCH; ++b) {
+            if (i0 + b * REDUCE_THREADS >= ns) break;
+            n += v[b].c.x;
+            sat += v[b].c.y;
+            nf += v[b].nf;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                a.s1[p] += v[b].s[p].x;
+                a.s2[p] += v[b].s[p].y;
+                if (CORR) {
+                    a.e1[p] += v[b].e[p].x;
+                    a.e2[p] += v[b].e[p].y;
+                }
+                if (INTS) {
+                    a.i1[p] += v[b].i1[p];
+                    const uint64_t lo = a.i2lo[p] + v[b].w[p].x;
+                    a.i2hi[p] += v[b].w[p].y + (lo < a.i2lo[p] ? 1u : 0u);
+                    a.i2lo[p] = lo;
+                }
             }
         }
     }
