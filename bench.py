@@ -8,7 +8,8 @@ uniforms; N_l (approximate) and M_l (correction) come from the nested optimal
 allocation at eps = 1e-3 in price units (variance eps^2, theta = 1) after an
 untimed pilot.  One step = all 18 (level, estimator) level sums in one launch
 sequence plus the host combination into the price estimate; consecutive steps are
-pipelined (the host marshals and enqueues step k + 1 while step k runs).
+pipelined (the host marshals and enqueues the next steps while step k runs, three
+steps in flight by default).
 
 Printed: one JSON line (metric path-steps/s), with the VALU roofline of the
 dominant kernel (the one with the most algorithmic work; HIP-event timing inside
@@ -250,7 +251,7 @@ def main():
                     help="instead: Poisson-arrival serving, p50/p99 latency (nested vs plain FP32)")
     ap.add_argument("--serve-rates", default="1000,5000,20000")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--depth", type=int, default=2,
+    ap.add_argument("--depth", type=int, default=3,
                     help="steps in flight: marshalled batches that alternate (1..4)")
     ap.add_argument("--tuning", default=None,
                     help="launch geometry as JSON (fields of mlmc_tuning) in place of the tuner")
@@ -308,8 +309,9 @@ def main():
     Na, Nc = N[:LEVELS], N[LEVELS:]
     path_steps = int(sum(int(Na[l]) << l for l in range(LEVELS)) + sum(int(Nc[l]) << l for l in range(LEVELS)))
 
-    # two marshalled batches alternate so that the host prepares step k + 1 while the
-    # GPU runs step k; each step draws fresh paths (path offsets advance)
+    # --depth marshalled batches (3 by default) rotate so that the host prepares the
+    # next steps while the GPU runs the current one, with room for the host's own
+    # pauses; each step draws fresh paths (path offsets advance)
     batches = [ctx.sums_batch(make_items(M, prob, prec_a, prec_c, Na, Nc, 0)) for _ in range(args.depth)]
     # launch geometry for this work list by the library's tuner (untimed), or the one
     # given (profiled runs: the tuner's timings are not those of an unprofiled run)
@@ -350,6 +352,10 @@ def main():
                     ests.append(combine_np(b.sums, scale))
                     top.append(level_mean(b.sums, LEVELS - 1, scale))
 
+    # per-kernel timing on during the warm-up too, so that its events exist before the
+    # timed region (they are created on first use); switching it on again clears the
+    # warm-up's launches from the statistics (all of them have landed)
+    ctx.set_timing(True)
     run_steps(args.warmup, False)
     host.update(enqueue_s=0.0, wait_s=0.0)
     ctx.set_timing(True)
