@@ -300,7 +300,7 @@ typedef struct mlmc_kernel_stat {
  *                 sequential chains); 0 disables.
  *   overlap_min_steps: launch sequences of at least this many fine path-steps
  *                 run their approximate-estimator kernels, with those works'
- *                 reduction and download, on a second stream beside the
+ *                 reduction, on a second stream beside the
  *                 exact-normal ones (each stream uploads its own copy of the plan,
  *                 so neither waits for the other); smaller sequences use the
  *                 context's stream alone.  Default 2^26. */

@@ -406,7 +406,7 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     }
     const bool fork = overlap && has_table && has_exact && ctx->aux_stream;
     // results are written in this order (position p holds work order[p]), so that
-    // each stream downloads one contiguous part
+    // each stream's reduction writes one contiguous part
     uint32_t n_red_aux = 0;
     f.order.clear();
     if (fork) {
@@ -489,7 +489,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         wdev[i].zbuf = reinterpret_cast<uint64_t>(d + zb_off[i] + align_up(pos * 4, 256));
     }
 
-    // 5. stage and upload [levels .. normal tiles], launch, download the results
+    // 5. stage and upload [levels .. normal tiles], launch; the reduction writes the
+    //    results into the staging buffer behind the plan
     const size_t up_bytes = o_end_plan - o_lvl;
     const size_t down_bytes = works.size() * sizeof(SlotDev);
     f.down_off = align_up(up_bytes, 256);
@@ -1084,7 +1085,7 @@ mlmc_status mlmc_set_tuning(mlmc_context* ctx, const mlmc_tuning* t) {
 
 // Launch-geometry tuner: coordinate descent over the tuning fields, each candidate
 // timed on the caller's own work list (host wall clock per launch sequence, planning,
-// upload, kernels, reduction and download, with sequences pipelined).
+// upload, kernels and reduction into pinned memory, with sequences pipelined).
 mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* works, uint32_t reps,
                           mlmc_tuning* out) {
     if (!ctx || !out) return MLMC_E_INVALID;

@@ -35,7 +35,7 @@ struct Tuning {
     uint64_t zb_max_paths = 1u << 15;
     uint64_t zb_max_positions = 1u << 22;
     // flights of at least this many fine path-steps run their table-only kernels on
-    // the second stream (a second plan upload and a second download, which small
+    // the second stream (a second plan upload and a second reduction launch, which small
     // flights do not win back)
     uint64_t overlap_min_steps = uint64_t(1) << 26;
 };

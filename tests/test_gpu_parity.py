@@ -123,6 +123,35 @@ def test_fp16_two_paths_per_lane_equal_debug_run(ctx, scheme, packed):
             assert a == b, (scheme, packed, pays, level)
 
 
+@pytest.mark.parametrize("est,arith,pays", [(M.EST_APPROX, "fixed", ("euro",)), (M.EST_APPROX, "fixed", PAYS),
+                                             (M.EST_CORR, "fp32", ("euro",))],
+                         ids=["fixed-one-payoff", "fixed-all-payoffs", "corr-fp32"])
+def test_many_tiles_reduction(ctx, est, arith, pays):
+    """A work cut into more than 8192 tiles (several batches of slot loads per lane of
+    the fixed-order reduction, and a ragged last one) against the same work in the
+    default tiles: the same path count and the same exact integer sums (every slot
+    added exactly once), FP64 sums within rounding."""
+    prob = M.make_problem("euler", pays, **GBM)
+    fmt = WIDE_FMT if arith == "fixed" else None
+    prec = M.make_precision(arith, 8, False, fmt)
+    n, off = 3_000_001, 17
+    ref = ctx.level_sums(prob, 2, n, off, prec, est, SEED)
+    saved = ctx.get_tuning()
+    ctx.set_tuning(tile_steps=256, min_tiles=1)
+    try:
+        small = ctx.level_sums(prob, 2, n, off, prec, est, SEED)
+    finally:
+        ctx.set_tuning(**saved)
+    for p in pays:
+        a, b = ref[p], small[p]
+        assert a["n"] == b["n"] == n, p
+        assert a["saturations"] == b["saturations"], p
+        if arith == "fixed":
+            assert a["isum1"] == b["isum1"] and a["isum2"] == b["isum2"], p
+        for k in ("sum1", "sum2", "esum1", "esum2"):
+            assert abs(a[k] - b[k]) <= 1e-10 * max(1.0, abs(a[k])), (p, k)
+
+
 def test_repeatable_and_offset_split(ctx):
     """Bit-identical repeated runs; exact integer sums split over two path ranges add up."""
     prob = M.make_problem("euler", ("euro", "asian"), **GBM)
