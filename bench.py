@@ -18,6 +18,7 @@ a bounded sample, and the time to RMSE eps of the nested estimator against plain
 FP32 MLMC on the same GPU.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -319,7 +320,7 @@ def main():
         ctx.set_tuning(**json.loads(args.tuning))
         tuning = ctx.get_tuning()
     else:
-        tuning = ctx.autotune(batches[0], reps=5)
+        tuning = ctx.autotune(batches[0], reps=20)
     off = N_PILOT
     ests, top = [], []
 
@@ -355,8 +356,16 @@ def main():
     # per-kernel timing on during the warm-up too, so that its events exist before the
     # timed region (they are created on first use); switching it on again clears the
     # warm-up's launches from the statistics (all of them have landed)
+    # no Python garbage collection from here through the timed region (as timeit
+    # does): a full collection stalls the host longer than the queued steps and leaves
+    # its caches cold; it runs before the warm-up, which warms them again
+    gc.collect()
+    gc.disable()
     ctx.set_timing(True)
-    run_steps(args.warmup, False)
+    # the warm-up takes the timed steps' own path, the per-step combination of the
+    # results included (its first calls are slow); its records are dropped
+    run_steps(args.warmup, True)
+    del done_at[:], ests[:], top[:]
     host.update(enqueue_s=0.0, wait_s=0.0)
     ctx.set_timing(True)
     torch.cuda.synchronize()
@@ -364,6 +373,7 @@ def main():
     run_steps(args.steps, True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gc.enable()
     stats = ctx.kernel_stats()
     ctx.set_timing(False)
     ms_step = dt * 1e3 / args.steps
