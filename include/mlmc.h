@@ -288,7 +288,7 @@ typedef struct mlmc_kernel_stat {
 
 /* Launch geometry of a context.  Results are reproducible for a fixed tuning;
  * FP64 sums may change in the last bits when it changes (summation order), integer
- * sums never do.  Defaults: 256, 256, 65536, 8, 2048, 32768, 4194304.
+ * sums never do.  Defaults: 256, 256, 131072, 16, 512, 32768, 4194304.
  *   block_table   threads per block of the table-only (APPROX) kernels, 64..1024
  *   block_exact   threads per block of kernels with exact normals, 64..256
  *   tile_steps    target fine path-steps per tile
@@ -322,7 +322,7 @@ mlmc_status mlmc_get_tuning(const mlmc_context* ctx, mlmc_tuning* out);
  * {2^14..2^18}, blocks_per_cu {2, 4, 8, 16}, min_tiles {512..4096} and zb_max_paths
  * {0, 2^13, 2^15, 2^17} and overlap_min_steps {0, 2^24, 2^26, 2^28, never},
  * starting from the context's current geometry and keeping
- * a change only when it is faster.  Sets the result on the context and copies it to
+ * a change only when it is at least 1% faster (timing noise does not move it).  Sets the result on the context and copies it to
  * out (out->struct_size must be set).  The works' sums are written by every trial
  * run (the last trial's remain); sums of the same work can differ in FP64 rounding
  * between geometries (a different tile split), so tune before pricing.  Errors:

@@ -1146,7 +1146,7 @@ mlmc_status mlmc_autotune(mlmc_context* ctx, uint32_t n, const mlmc_level_work* 
             const mlmc_status st = measure(t, sec);
             if (st == MLMC_E_NOMEM) continue;                 // a geometry the workspace cannot hold
             if (st != MLMC_OK) return st;
-            if (sec < best_s) {
+            if (sec < 0.99 * best_s) {                       // at least 1% faster
                 best_s = sec;
                 best = t;
             }

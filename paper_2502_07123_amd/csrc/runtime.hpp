@@ -27,9 +27,9 @@ namespace mlmc {
 struct Tuning {
     uint32_t block_table = 256;     // threads per block, table-only kernels
     uint32_t block_exact = 256;     // threads per block, kernels with exact normals
-    uint32_t tile_steps = 1u << 16; // path-steps per tile (target)
-    uint32_t blocks_per_cu = 8;     // persistent grid = CUs * blocks_per_cu (cap)
-    uint32_t min_tiles = 2048;      // a work is split into at least this many tiles when it can be
+    uint32_t tile_steps = 1u << 17; // path-steps per tile (target)
+    uint32_t blocks_per_cu = 16;    // persistent grid = CUs * blocks_per_cu (cap)
+    uint32_t min_tiles = 512;       // a work is split into at least this many tiles when it can be
     // exact-normal works with at most zb_max_paths paths (and zb_max_positions
     // stream positions) get their normals computed ahead, off the paths' chains
     uint64_t zb_max_paths = 1u << 15;

@@ -19,7 +19,8 @@ def ctx():
 
 
 def _n_for(level):
-    # several tiles (2^16 path-steps each) and a ragged tail at every level
+    # several tiles (one block's worth of groups at least per tile) and a ragged tail
+    # at every level
     return int(max(3 * (1 << 16) // max(1 << level, 16) + 77, 2000))
 
 
