@@ -619,7 +619,7 @@ mlmc_status engine_run_batch(mlmc_context* ctx, std::vector<OptionRun>& runs) {
             launched += 1;
         }
         const int k = landed & 1;
-        hipError_t e = wait_event(E->ev_done[k]);
+        hipError_t e = hipEventSynchronize(E->ev_done[k]);
         if (e != hipSuccess) return fail(ctx, MLMC_E_DEVICE, std::string("sweep: ") + hipGetErrorString(e));
         landed += 1;
         const uint32_t* stw = E->status_h[k];
@@ -647,7 +647,7 @@ mlmc_status engine_run_batch(mlmc_context* ctx, std::vector<OptionRun>& runs) {
     }
     // the sweep still in flight does nothing for finished runs; then the states
     while (landed < launched) {
-        hipError_t e = wait_event(E->ev_done[landed & 1]);
+        hipError_t e = hipEventSynchronize(E->ev_done[landed & 1]);
         if (e != hipSuccess) return fail(ctx, MLMC_E_DEVICE, std::string("sweep: ") + hipGetErrorString(e));
         landed += 1;
     }

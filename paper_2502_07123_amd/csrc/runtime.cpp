@@ -182,22 +182,13 @@ uint32_t lds_bytes_for(const Variant& v, const LevelDev& L) {
     return L.table_bytes + extra;
 }
 
-hipError_t wait_event(hipEvent_t e) {
-    const double t0 = now_seconds();
-    for (;;) {
-        const hipError_t q = hipEventQuery(e);
-        if (q != hipErrorNotReady) return q;
-        if (now_seconds() - t0 > SPIN_WAIT_SECONDS) return hipEventSynchronize(e);
-    }
-}
-
 // Waits for a flight, copies its results (to out, or to the mlmc_sums of its
 // enqueued work list) and returns its staging buffer and events to the pools.
 mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out) {
-    hipError_t e = wait_event(f.done);
+    hipError_t e = hipEventSynchronize(f.done);
     ctx->ev_plain.push_back(f.done);
     if (f.done_aux) {
-        const hipError_t e2 = wait_event(f.done_aux);
+        const hipError_t e2 = hipEventSynchronize(f.done_aux);
         if (e == hipSuccess) e = e2;
         ctx->ev_plain.push_back(f.done_aux);
     }

@@ -201,10 +201,4 @@ mlmc_status run_sweeps(mlmc_context* ctx, std::vector<OptionRun*>& opts);
 mlmc_status sweep_once(mlmc_context* ctx, const std::vector<OptionRun*>& opts, bool& ran);
 double now_seconds();
 
-// Waits for a device event: polls it for up to SPIN_WAIT_SECONDS (a launch sequence
-// or a sweep lands within that), then blocks.  The waiting thread stays awake for
-// short waits, so it acts on the result without a wake-up delay.
-constexpr double SPIN_WAIT_SECONDS = 1e-3;
-hipError_t wait_event(hipEvent_t e);
-
 }  // namespace mlmc
