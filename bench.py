@@ -268,7 +268,7 @@ def main():
     if not 1 <= args.depth <= 4:
         ap.error("--depth must be 1..4")
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
