@@ -9,7 +9,8 @@
 //   branch), degrees 24 and 20, w from the logarithm log_unit below
 //   (gen_norminv_f64.py); relative error below 5e-16 on the 32-bit grid.
 // FP32: w < 5, degrees 9 and 9 (gen_norminv_f32.py); relative error below 3e-7.
-// Both take J directly so that 2U - 1 and min(U, 1 - U) are formed exactly.
+// Both take J directly so that 2U - 1 (and, in FP32, min(U, 1 - U)) are formed
+// exactly.
 #pragma once
 #include <cmath>
 #include <cstdint>
@@ -66,12 +67,13 @@ struct NinvArg {
     T y, w;
 };
 
+// 4U(1-U) = 1 - y^2 exactly, so the fma's single rounding gives the same double as
+// rounding us (1 - us) with us = min(U, 1 - U) (1 - us and the scaling by 4 are
+// exact), in one instruction instead of the second conversion and three products.
 __host__ __device__ __forceinline__ NinvArg<double> ninv64_arg(uint32_t J) {
     const int32_t sj = static_cast<int32_t>(J ^ 0x80000000u);
     const double y = (static_cast<double>(sj) + 0.5) * 0x1p-31;       // 2U - 1, exact
-    const uint32_t v = (J < 0x80000000u) ? J : ~J;
-    const double us = (static_cast<double>(v) + 0.5) * 0x1p-32;       // min(U, 1-U), exact
-    return NinvArg<double>{y, -log_unit((us * (1.0 - us)) * 4.0)};
+    return NinvArg<double>{y, -log_unit(fma(-y, y, 1.0))};
 }
 
 __host__ __device__ __forceinline__ double ninv64_central(const NinvArg<double>& a) {
@@ -90,9 +92,13 @@ __host__ __device__ __forceinline__ double ninv64_tail(const NinvArg<double>& a)
     // The tail runs for about 1e-3 of the inputs: its coefficients are loaded where it
     // runs (the empty asm hides the table's address, so the loads are not hoisted out
     // of the callers' loops), which leaves the loops' scalar registers to the central
-    // polynomial instead of spilling them into vector-register lanes.
-    const double* pt = g_ninv64_pt;
-    asm volatile("" : "+s"(pt));
+    // polynomial instead of spilling them into vector-register lanes.  The address is
+    // uniform and the table read-only: through the constant address space the loads
+    // are scalar and issued together, one wait instead of one per coefficient pair.
+    const double* pg = g_ninv64_pt;
+    asm volatile("" : "+s"(pg));
+    const __attribute__((address_space(4))) double* pt =
+        (const __attribute__((address_space(4))) double*)pg;
 #else
     const double* pt = NINV64_PT;
 #endif
