@@ -121,6 +121,8 @@ def evaluate(cc, cmid, ct, tmid, J):
     y = (sj.astype(np.float64) + 0.5) * 2.0 ** -31                 # 2u - 1, exact
     v = np.minimum(J, 2 ** 32 - 1 - J).astype(np.float64)
     us = (v + 0.5) * 2.0 ** -32                                    # min(u, 1 - u), exact
+    # the kernels form 4u(1-u) as the single fma 1 - y^2: the same double, since the
+    # real values agree and each form rounds once
     w = -log_unit((us * (1.0 - us)) * 4.0)
     out = np.empty(J.shape)
     cen = w < W1
