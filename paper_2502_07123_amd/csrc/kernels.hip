@@ -117,9 +117,11 @@ k_paths(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ co
 // (PathBody::exact0_group, the four inverse normals interleaved).  The correction
 // estimator's approximate-side sample is a function of the table index, tabulated
 // per level in LDS (ya_sample) after the step table.  Same per-path operations,
-// tiles and block reduction as k_paths, so the sums are the same bit for bit.
+// tiles and block reduction as k_paths, so the sums are the same bit for bit.  At
+// most five waves per SIMD for one payoff, four for all five (whose state would
+// otherwise spill to scratch).
 template <int EST, int ARITH, bool MIL, int NP, bool TRACK, bool X32>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NP == 1 ? 5 : 4)))
 k_exact0(const WorkTilesDev* __restrict__ wtiles, const uint32_t* __restrict__ counts,
          const WorkDev* __restrict__ works, const LevelDev* __restrict__ levels,
          const uint8_t* __restrict__ tables, TileSlot* __restrict__ slots) {
