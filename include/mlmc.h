@@ -178,8 +178,10 @@ typedef struct mlmc_context mlmc_context;
  * sub-allocates for tables, work lists and sums; it is the context's HBM budget
  * (MLMC_E_NOMEM when a call needs more).  The caller owns it and keeps it alive
  * until mlmc_context_destroy.  NULL asks the library to allocate workspace_bytes
- * itself (freed at destroy).  stream: the hipStream_t every launch goes to (NULL:
- * the null stream).  Errors: MLMC_E_INVALID (bad device, size < 1 MiB),
+ * itself (freed at destroy).  stream: the hipStream_t launches go to (NULL: the
+ * null stream); large launch sequences also use two streams the context creates
+ * (see overlap_min_steps), and the library waits for those too before it reports
+ * their results.  Errors: MLMC_E_INVALID (bad device, size < 1 MiB),
  * MLMC_E_DEVICE (HIP failure). */
 mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t workspace_bytes,
                                 void* stream, mlmc_context** out);
@@ -302,8 +304,10 @@ typedef struct mlmc_kernel_stat {
  *                 run their approximate-estimator kernels, with those works'
  *                 reduction, on a second stream beside the
  *                 exact-normal ones (each stream uploads its own copy of the plan,
- *                 so neither waits for the other); smaller sequences use the
- *                 context's stream alone.  Default 2^26. */
+ *                 so neither waits for the other), and their level-0 exact-normal
+ *                 kernels on a third stream (it waits for the context stream's
+ *                 upload; that stream's reduction waits for it); smaller sequences
+ *                 use the context's stream alone.  Default 2^26. */
 typedef struct mlmc_tuning {
     uint32_t struct_size;
     uint32_t block_table, block_exact;

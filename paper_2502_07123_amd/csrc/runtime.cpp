@@ -192,6 +192,9 @@ mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out)
         if (e == hipSuccess) e = e2;
         ctx->ev_plain.push_back(f.done_aux);
     }
+    // the first stream waited for the level-0 stream before recording done
+    if (f.ev_plan) ctx->ev_plain.push_back(f.ev_plan);
+    if (f.ev_l0) ctx->ev_plain.push_back(f.ev_l0);
     PinnedBuf& pb = ctx->pins[f.pin];
     pb.busy = false;
     if (e != hipSuccess) {
@@ -524,6 +527,19 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     f.n_works = static_cast<uint32_t>(works.size());
     if ((st = take_event(ctx, false, f.done)) != MLMC_OK) return st;
     if (fork && (st = take_event(ctx, false, f.done_aux)) != MLMC_OK) return st;
+    // In a two-stream flight the level-0 exact-normal kernels run on a third stream,
+    // beside the other exact levels' long serial paths (which leave most of the
+    // machine idle); they read the first stream's plan once its upload is done.
+    bool split_l0 = false;
+    if (fork && ctx->l0_stream)
+        for (auto& kv : groups)
+            if (kv.second.n_tiles && kv.second.v.l0 && kv.second.v.est != MLMC_EST_APPROX) split_l0 = true;
+    if (split_l0) {
+        if ((st = take_event(ctx, false, f.ev_plan)) != MLMC_OK) return st;
+        if ((st = take_event(ctx, false, f.ev_l0)) != MLMC_OK) return st;
+        HIPCHK(hipEventRecord(f.ev_plan, s));
+        HIPCHK(hipStreamWaitEvent(ctx->l0_stream, f.ev_plan, 0));
+    }
     // the second stream's copy of the plan
     uint8_t* da = fork ? d + (o_copy - o_lvl) : d;
     // exact normals ahead of the path kernels for the buffered works
@@ -546,7 +562,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
         const uint32_t nt = g.n_tiles;
         if (!nt) continue;
         const bool on_aux = fork && g.v.est == MLMC_EST_APPROX;
-        hipStream_t gs = on_aux ? sa : s;
+        const bool on_l0 = split_l0 && g.v.l0 && g.v.est != MLMC_EST_APPROX;
+        hipStream_t gs = on_aux ? sa : (on_l0 ? ctx->l0_stream : s);
         uint8_t* dp = on_aux ? da : d;           // plan copy of that stream
         const uint32_t grid = std::min(nt, max_grid);
         Flight::Timed tm{};
@@ -570,6 +587,10 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     // host memory): they are on the host when the kernel completes
     const TileSlot* sl_dev = reinterpret_cast<const TileSlot*>(d + o_slot);
     SlotDev* res_host = reinterpret_cast<SlotDev*>(h + f.down_off);
+    if (split_l0) {
+        HIPCHK(hipEventRecord(f.ev_l0, ctx->l0_stream));
+        HIPCHK(hipStreamWaitEvent(s, f.ev_l0, 0));
+    }
     if (fork) {
         // each stream reduces its own works (positions [0, n_red_aux) on the second
         // stream) and records its own completion event
@@ -911,7 +932,13 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
         delete ctx;
         return MLMC_E_DEVICE;
     }
+    if (hipStreamCreateWithFlags(&ctx->l0_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(ctx->aux_stream);
+        delete ctx;
+        return MLMC_E_DEVICE;
+    }
     if (hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        (void)hipStreamDestroy(ctx->l0_stream);
         (void)hipStreamDestroy(ctx->aux_stream);
         delete ctx;
         return MLMC_E_DEVICE;
@@ -920,6 +947,7 @@ mlmc_status mlmc_context_create(int32_t device, void* workspace, uint64_t worksp
         ctx->ws = static_cast<uint8_t*>(workspace);
     } else {
         if (hipMalloc(reinterpret_cast<void**>(&ctx->ws), workspace_bytes) != hipSuccess) {
+            (void)hipStreamDestroy(ctx->l0_stream);
             (void)hipStreamDestroy(ctx->aux_stream);
             delete ctx;
             return MLMC_E_NOMEM;
@@ -939,9 +967,11 @@ void mlmc_context_destroy(mlmc_context* ctx) {
         ctx->engines.clear();
     }
     if (ctx->aux_stream) (void)hipStreamSynchronize(ctx->aux_stream);
+    if (ctx->l0_stream) (void)hipStreamSynchronize(ctx->l0_stream);
     for (hipEvent_t e : ctx->ev_plain) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_timed) (void)hipEventDestroy(e);
     if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
+    if (ctx->l0_stream) (void)hipStreamDestroy(ctx->l0_stream);
     for (auto& pb : ctx->pins)
         if (pb.p) (void)hipHostFree(pb.p);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);

@@ -91,6 +91,8 @@ struct Flight {
     uint32_t n_works = 0;
     hipEvent_t done = nullptr;
     hipEvent_t done_aux = nullptr;  // the second stream's part (two-stream flights)
+    hipEvent_t ev_plan = nullptr;   // the plan uploaded (the level-0 stream waits for it)
+    hipEvent_t ev_l0 = nullptr;     // the level-0 exact-normal kernels done
     std::vector<uint32_t> order;    // two-stream flights: result position -> work
     struct Timed {
         Variant v;
@@ -109,6 +111,7 @@ struct mlmc_context {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t aux_stream = nullptr;    // table-only path kernels beside the exact-normal ones
+    hipStream_t l0_stream = nullptr;     // level-0 exact-normal kernels beside the other exact levels
     bool own_ws = false;
     uint8_t* ws = nullptr;
     uint64_t ws_bytes = 0;
