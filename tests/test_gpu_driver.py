@@ -293,22 +293,32 @@ def test_autotune_keeps_results_valid():
         c.close()
 
 
+def _items_with_level0(off=0):
+    """_items plus level-0 works of the exact-normal estimators (the level-0 kernel,
+    on the third stream of a two-stream flight)."""
+    mil = M.make_problem("milstein", ("euro", "asian"), **GBM)
+    eul = M.make_problem("euler", ("euro",), **GBM)
+    return _items(off) + [(mil, 0, 50_001, off, M.make_precision("fp32", 8), M.EST_CORR, SEED, 5),
+                          (eul, 0, 30_000, off, M.make_precision("fp64"), M.EST_PLAIN, SEED, 6)]
+
+
 @pytest.mark.parametrize("how", ["sync", "enqueued", "estimate", "server"])
 def test_two_stream_flights_equal_one_stream(how):
     """Flights that put the approximate works on the second stream (each stream with
-    its own plan copy, reduction and download, results returned in work order) give
-    the same sums as one-stream flights: synchronous batches, several enqueued
-    batches in flight, and an adaptive estimate."""
+    its own plan copy, reduction and download, results returned in work order) and
+    the level-0 exact-normal works on a third give the same sums as one-stream
+    flights: synchronous batches, several enqueued batches in flight, an adaptive
+    estimate and the server."""
     c = M.Context(0, workspace_bytes=256 << 20)
     try:
-        items = _items()
+        items = _items_with_level0()
         runs = []
         for thr in ((1 << 64) - 1, 0):
             c.set_tuning(overlap_min_steps=thr)
             if how == "sync":
                 runs.append(c.level_sums_batch(items))
             elif how == "enqueued":
-                bs = [c.sums_batch(_items(off=1000 * k)) for k in range(3)]
+                bs = [c.sums_batch(_items_with_level0(off=1000 * k)) for k in range(3)]
                 for b in bs:
                     b.enqueue()
                 out = []
