@@ -303,11 +303,12 @@ typedef struct mlmc_kernel_stat {
  *   overlap_min_steps: launch sequences of at least this many fine path-steps
  *                 run their approximate-estimator kernels, with those works'
  *                 reduction, on a second stream beside the
- *                 exact-normal ones (each stream uploads its own copy of the plan,
- *                 so neither waits for the other), and their level-0 exact-normal
- *                 kernels on a third stream (it waits for the context stream's
- *                 upload; that stream's reduction waits for it); smaller sequences
- *                 use the context's stream alone.  Default 2^26. */
+ *                 exact-normal ones (with its own copy of the plan, uploaded on a
+ *                 third stream, so that neither waits for the other), and their
+ *                 level-0 exact-normal kernels on the third stream (it waits for
+ *                 the context stream's upload; that stream's reduction waits for
+ *                 it); smaller sequences use the context's stream alone.  Default
+ *                 2^26. */
 typedef struct mlmc_tuning {
     uint32_t struct_size;
     uint32_t block_table, block_exact;

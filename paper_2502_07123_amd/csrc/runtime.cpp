@@ -195,6 +195,7 @@ mlmc_status land_flight(mlmc_context* ctx, Flight& f, std::vector<SlotDev>* out)
     // the first stream waited for the level-0 stream before recording done
     if (f.ev_plan) ctx->ev_plain.push_back(f.ev_plan);
     if (f.ev_l0) ctx->ev_plain.push_back(f.ev_l0);
+    if (f.ev_up2) ctx->ev_plain.push_back(f.ev_up2);
     PinnedBuf& pb = ctx->pins[f.pin];
     pb.busy = false;
     if (e != hipSuccess) {
@@ -448,8 +449,8 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     }
     const size_t o_cnt = align_up(o_nt1 + ntiles[1].size() * sizeof(TileDev), 256);
     const size_t o_end_plan = align_up(o_cnt + counts.size() * sizeof(uint32_t), 256);
-    // the second stream reads its own copy of the plan (uploaded on that stream, so
-    // neither stream waits for the other)
+    // the second stream reads its own copy of the plan (uploaded on the third stream,
+    // so that neither of the first two streams waits for the other)
     const size_t o_copy = o_end_plan;
     const size_t o_slot = fork ? align_up(o_copy + (o_end_plan - o_lvl), 256) : o_end_plan;
     size_t o_zb = align_up(o_slot + size_t(n_slots) * sizeof(TileSlot), 256);
@@ -515,8 +516,11 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     if (!counts.empty()) std::memcpy(h + (o_cnt - o_lvl), counts.data(), counts.size() * sizeof(uint32_t));
     hipStream_t s = ctx->stream;
     hipStream_t sa = fork ? ctx->aux_stream : s;
+    // The second stream's plan copy is uploaded on the third stream, so that it does
+    // not queue behind the previous flight's approximate kernel and reduction.
+    hipStream_t s_up2 = ctx->l0_stream ? ctx->l0_stream : sa;
     hipError_t ue = launch_upload(h, d + o_lvl, up_bytes, s);
-    if (ue == hipSuccess && fork) ue = launch_upload(h, d + o_copy, up_bytes, sa);
+    if (ue == hipSuccess && fork) ue = launch_upload(h, d + o_copy, up_bytes, s_up2);
     if (ue != hipSuccess) {
         release();
         return fail(ctx, MLMC_E_DEVICE, std::string("upload: ") + hipGetErrorString(ue));
@@ -527,6 +531,11 @@ mlmc_status launch_flight(mlmc_context* ctx, const std::vector<WorkSpec>& works,
     f.n_works = static_cast<uint32_t>(works.size());
     if ((st = take_event(ctx, false, f.done)) != MLMC_OK) return st;
     if (fork && (st = take_event(ctx, false, f.done_aux)) != MLMC_OK) return st;
+    if (fork && s_up2 != sa) {
+        if ((st = take_event(ctx, false, f.ev_up2)) != MLMC_OK) return st;
+        HIPCHK(hipEventRecord(f.ev_up2, s_up2));
+        HIPCHK(hipStreamWaitEvent(sa, f.ev_up2, 0));
+    }
     // In a two-stream flight the level-0 exact-normal kernels run on a third stream,
     // beside the other exact levels' long serial paths (which leave most of the
     // machine idle); they read the first stream's plan once its upload is done.

@@ -93,6 +93,7 @@ struct Flight {
     hipEvent_t done_aux = nullptr;  // the second stream's part (two-stream flights)
     hipEvent_t ev_plan = nullptr;   // the plan uploaded (the level-0 stream waits for it)
     hipEvent_t ev_l0 = nullptr;     // the level-0 exact-normal kernels done
+    hipEvent_t ev_up2 = nullptr;    // the second stream's plan copy uploaded
     std::vector<uint32_t> order;    // two-stream flights: result position -> work
     struct Timed {
         Variant v;
